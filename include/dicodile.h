@@ -1,0 +1,179 @@
+/*
+ * dicodile.h -- C ABI of the MI355X (gfx950) convolutional sparse coding
+ * library built on the CSC step of DiCoDiLe (Moreau & Gramfort,
+ * "Distributed Convolutional Dictionary Learning (DiCoDiLe): Pattern
+ * Discovery in Large Images and Signals", arXiv:1901.09235).
+ *
+ * Problem (Sec. 2, eq. csc):  Z* = argmin_Z 1/2 ||X - Z*D||_2^2 + lambda ||Z||_1,
+ * optionally with Z >= 0.  Solver: locally greedy coordinate descent (Alg. 1)
+ * on a grid of workers with the soft-lock rule (Alg. 3, eq. soft_lock); one
+ * worker is one GPU workgroup.
+ *
+ * Conventions shared by every call (0-based, row-major, contiguous):
+ *   d = 1 (signals): X (P, T),      D (K, P, L),      Z (K, T - L + 1)
+ *   d = 2 (images):  X (P, T1, T2), D (K, P, L1, L2), Z (K, T1-L1+1, T2-L2+1)
+ *   Z lives on the "valid" domain, so that every shifted atom keeps the norm
+ *   ||D_k||_2^2 that the closed-form update of eq. pb_coord divides by.
+ *   (Z*D)_p[x] = sum_k sum_t Z_k[x - t] D_{k,p}[t]               (eq. model)
+ *   corr(R, D)_k[w] = sum_p sum_t D_{k,p}[t] R_p[w + t]  (the paper's R * D~_k)
+ *
+ * Memory: every array argument is a caller-owned DEVICE pointer (memory of
+ * the current HIP device, e.g. a torch tensor's data_ptr()), in the dtype
+ * given by the call, unless stated otherwise.  The library never frees caller
+ * memory.  It keeps a per-device workspace that grows on demand and is
+ * released by dicodile_release().
+ *
+ * Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ * stream).  Every call enqueues its work on that stream and returns after the
+ * work has completed (the calls fill host-side results).
+ *
+ * Errors: every call returns a dcdl_status.  On an error (< 0) no caller
+ * buffer is written, except where stated; dicodile_last_error() returns a
+ * message for the calling thread.  Concurrent calls on the same device are
+ * serialised by the library.
+ */
+#ifndef DICODILE_MI355X_H
+#define DICODILE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DCDL_OK = 0,
+  DCDL_NOT_CONVERGED = 1, /* stopped on max_updates / max_rounds / timeout; z holds the iterate */
+  DCDL_EINVAL = -1,       /* bad shape, dtype, option or pointer */
+  DCDL_ENOMEM = -2,       /* device memory or HBM budget exhausted */
+  DCDL_EHIP = -3,         /* a HIP runtime call failed */
+  DCDL_EDIVERGED = -4,    /* divergence guard: ||Z||_inf exceeded opts.div_guard */
+  DCDL_ETIMEOUT = -5,     /* a worker waited on a neighbour past the internal limit */
+  DCDL_ENODEV = -6        /* no gfx950 device, or the call needs a capability it lacks */
+} dcdl_status;
+
+typedef enum { DCDL_F32 = 0, DCDL_F64 = 1 } dcdl_dtype;
+
+/* Problem shape.  ndim = 1: T[0] = T, L[0] = L (T[1], L[1] ignored).
+ * ndim = 2: T = (T1, T2), L = (L1, L2).  Requires 1 <= L_i <= T_i, P >= 1,
+ * 1 <= K <= 1024. */
+typedef struct {
+  int32_t ndim;
+  int32_t P;
+  int32_t K;
+  int32_t reserved;
+  int64_t T[2];
+  int32_t L[2];
+} dcdl_shape;
+
+/* Solver options (dicodile_csc).  Zero-initialise, then set lambda and tol. */
+typedef struct {
+  double lambda;          /* absolute lambda > 0 (Sec. 2: set as a fraction of lambda_max) */
+  double tol;             /* epsilon >= 0 on |Delta Z| (Alg. 1 stopping rule) */
+  int32_t positive;       /* 1: constrain Z >= 0 (one-sided soft-thresholding) */
+  int32_t certify;        /* 1 (recommended): support- or sign-changing moves score at
+                             least tol, so exit bounds the strict KKT violation by
+                             max_k ||D_k||^2 tol; 0: the paper's plain |Delta Z| rule */
+  dcdl_dtype dtype;       /* precision of X, D, z_out and of the incremental beta/Z */
+  int32_t no_soft_lock;   /* 1: disable the soft-lock test of eq. soft_lock (ablation of
+                             Sec. 5 only; pair it with div_guard) */
+  int32_t threads;        /* threads per worker workgroup: 64 ... 1024 (powers of 2); 0 -> 256 */
+  int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
+  int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library */
+  int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
+  int32_t refresh_every;  /* recompute beta from its definition every this many sweeps
+                             (drift correction, FP64 contraction); 0 -> only at the end */
+  int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
+  int32_t reserved;
+  int64_t max_rounds;     /* cap on worker rounds (0 -> unlimited) */
+  double div_guard;       /* stop with DCDL_EDIVERGED if |Z| exceeds this (0 -> off) */
+  double timeout_s;       /* wall-clock cap for the whole call (0 -> none) */
+  double kkt_target;      /* final strict-KKT acceptance, in units of lambda; 0 -> 1e-4 */
+} dcdl_csc_opts;
+
+/* Filled by dicodile_csc when `info` is not NULL (host memory). */
+typedef struct {
+  int64_t n_updates;      /* accepted coordinate updates */
+  int64_t n_candidates;   /* candidates with score >= tol */
+  int64_t n_softlocked;   /* candidates rejected by the soft-lock test */
+  int64_t n_rounds;       /* rounds of the busiest worker */
+  int64_t n_sweeps;       /* completed sweeps (every sub-domain visited once) */
+  int64_t n_nonzero;      /* non-zeros of the returned Z */
+  double objective;       /* FP64 F(Z) of the returned Z */
+  double kkt;             /* FP64 strict KKT violation of the returned Z, / lambda */
+  double lambda_max;      /* FP64 ||corr(X, D)||_inf (one-sided if positive) */
+  double t_total_s;       /* wall time of the call */
+  double t_init_s;        /* DtD, beta init */
+  double t_cd_s;          /* coordinate-descent rounds */
+  double t_check_s;       /* final FP64 objective / KKT check (and refreshes) */
+  int32_t converged;      /* 1: exit certificate met and final check passed */
+  int32_t grid[2];        /* worker grid used */
+  int32_t tile[2];        /* sub-domain size used */
+  int32_t n_passes;       /* solve passes (1 + polish passes) */
+  int32_t reserved;
+  int64_t n_visits;       /* sub-domain visits (worker rounds with a sub-domain to scan) */
+  int64_t n_checked;      /* positions read by soft-lock tests */
+  int64_t n_patched;      /* positions of beta patched by accepted updates */
+  double t_worker_wait_s;    /* per-worker average time waiting on neighbours' progress */
+  double t_worker_select_s;  /* ... selecting, soft-lock testing and publishing candidates */
+  double t_worker_collect_s; /* ... waiting for the neighbours' candidates */
+  double t_worker_apply_s;   /* ... applying accepted updates to beta, z and the move cache */
+} dcdl_csc_info;
+
+/* Library version string (static storage). */
+const char *dicodile_version(void);
+
+/* Message of the last error on the calling thread ("" if none). */
+const char *dicodile_last_error(void);
+
+/* Release the per-device workspace and cached tables of the current device. */
+int dicodile_release(void);
+
+/* DtD (Sec. 3, the kernel of eq. beta_update):
+ *   dtd[k0][k][tau + L - 1] = sum_p sum_t D_{k0,p}[t] D_{k,p}[t + tau],
+ *   tau in Phi = [-L+1, L-1]^d.
+ * D: (K, P, L...) device, dtype.  dtd_out: (K, K, 2L1-1[, 2L2-1]) device, dtype. */
+int dicodile_dtd(const dcdl_shape *shape, dcdl_dtype dtype, const void *D, void *dtd_out,
+                 void *stream);
+
+/* lambda_max = max_{k,w} |corr(X, D)_k[w]| (Sec. 2, CSC paragraph: for
+ * lambda >= lambda_max the zero activation is optimal).  positive = 1 gives
+ * the one-sided bound max(max corr, 0).  Computed in FP64 whatever dtype X
+ * and D have.  out: host double. */
+int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D,
+                        int32_t positive, double *out, void *stream);
+
+/* Solve eq. csc with LGCD + soft-lock on a grid of workgroups (Alg. 1, Alg. 3).
+ * X: (P, T...) device, opts->dtype.  D: (K, P, L...) device, opts->dtype.
+ * z_out: (K, T-L+1 ...) device, opts->dtype; read first if opts->warm_start.
+ * info: host, may be NULL.
+ * Returns DCDL_OK when the sweep certificate (no move scoring >= tol) and the
+ * FP64 final check (strict KKT <= kkt_target) both hold; DCDL_NOT_CONVERGED
+ * with the current iterate in z_out when a cap stopped it.  The incremental
+ * beta and Z are kept in opts->dtype; the final objective/KKT are FP64. */
+int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D,
+                 const dcdl_csc_opts *opts, void *z_out, dcdl_csc_info *info, void *stream);
+
+/* FP64 objective F(Z) = 1/2||X - Z*D||^2 + lambda ||Z||_1 and strict KKT
+ * violation / lambda (with g = corr(X - Z*D, D): max(|g| - lambda, 0) on
+ * zeros, |g - lambda sign Z| on the support; one-sided if positive).
+ * X, D, z: device, dtype.  objective, kkt: host doubles (either may be NULL). */
+int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void *X,
+                           const void *D, const void *z, double lambda, int32_t positive,
+                           double *objective, double *kkt, void *stream);
+
+/* Sufficient statistics of the dictionary update (Sec. 4.2, eq. phi):
+ *   ztz[k][k'][tau + L - 1] = sum_w Z_k[w] Z_k'[w + tau],  tau in Phi
+ *   ztX[k][p][t]            = sum_w Z_k[w] X_p[w + t],     t in Theta
+ * z: (K, T-L+1 ...) device, dtype.  X: (P, T...) device, dtype.
+ * ztz_out: (K, K, 2L-1 ...) device, dtype.  ztX_out: (K, P, L...) device, dtype.
+ * Accumulation is in FP64 over the non-zeros of z. */
+int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, const void *z, const void *X,
+                        void *ztz_out, void *ztX_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DICODILE_MI355X_H */

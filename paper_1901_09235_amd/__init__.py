@@ -1,0 +1,294 @@
+"""MI355X (gfx950) convolutional sparse coding: the CSC step of DiCoDiLe.
+
+Python binding of the C ABI in ``include/dicodile.h``.  The functions here only
+marshal arguments: every step of the solve runs in the HIP library
+``_build/libdicodile_mi355x.so`` (build it with
+``python -m paper_1901_09235_amd.build``).  PyTorch provides device memory
+and the current stream.  If the library is missing, every call raises.
+
+Problem (arXiv:1901.09235, Sec. 2, eq. csc):
+    Z* = argmin_Z 1/2 ||X - Z*D||^2 + lambda ||Z||_1   (optionally Z >= 0)
+Shapes: signals X (P, T), D (K, P, L), Z (K, T-L+1);
+        images  X (P, T1, T2), D (K, P, L1, L2), Z (K, T1-L1+1, T2-L2+1).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
+           "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
+           "dicodile_dict_stats", "dicodile_release", "STATUS"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_build", "libdicodile_mi355x.so")
+_lib = None
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
+          -4: "EDIVERGED", -5: "ETIMEOUT", -6: "ENODEV"}
+F32, F64 = 0, 1
+
+
+class DicodileError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("P", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("T", ctypes.c_int64 * 2), ("L", ctypes.c_int32 * 2)]
+
+
+class CscOpts(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("tol", ctypes.c_double),
+                ("positive", ctypes.c_int32), ("certify", ctypes.c_int32),
+                ("dtype", ctypes.c_int32), ("no_soft_lock", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("tile", ctypes.c_int32 * 2),
+                ("grid", ctypes.c_int32 * 2), ("warm_start", ctypes.c_int32),
+                ("refresh_every", ctypes.c_int32), ("max_polish", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
+                ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
+                ("kkt_target", ctypes.c_double)]
+
+
+class CscInfo(ctypes.Structure):
+    _fields_ = [("n_updates", ctypes.c_int64), ("n_candidates", ctypes.c_int64),
+                ("n_softlocked", ctypes.c_int64), ("n_rounds", ctypes.c_int64),
+                ("n_sweeps", ctypes.c_int64), ("n_nonzero", ctypes.c_int64),
+                ("objective", ctypes.c_double), ("kkt", ctypes.c_double),
+                ("lambda_max", ctypes.c_double), ("t_total_s", ctypes.c_double),
+                ("t_init_s", ctypes.c_double), ("t_cd_s", ctypes.c_double),
+                ("t_check_s", ctypes.c_double), ("converged", ctypes.c_int32),
+                ("grid", ctypes.c_int32 * 2), ("tile", ctypes.c_int32 * 2),
+                ("n_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_visits", ctypes.c_int64), ("n_checked", ctypes.c_int64),
+                ("n_patched", ctypes.c_int64), ("t_worker_wait_s", ctypes.c_double),
+                ("t_worker_select_s", ctypes.c_double), ("t_worker_collect_s", ctypes.c_double),
+                ("t_worker_apply_s", ctypes.c_double)]
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load():
+    """Load the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise DicodileError(-6, f"HIP library not built: {_LIB_PATH} is missing "
+                                "(run python -m paper_1901_09235_amd.build)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    vp, i32, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    sp = ctypes.POINTER(Shape)
+    lib.dicodile_version.restype = ctypes.c_char_p
+    lib.dicodile_last_error.restype = ctypes.c_char_p
+    lib.dicodile_release.restype = ctypes.c_int
+    lib.dicodile_dtd.argtypes = [sp, i32, vp, vp, vp]
+    lib.dicodile_lambda_max.argtypes = [sp, i32, vp, vp, i32, ctypes.POINTER(dbl), vp]
+    lib.dicodile_csc.argtypes = [sp, vp, vp, ctypes.POINTER(CscOpts), vp, ctypes.POINTER(CscInfo), vp]
+    lib.dicodile_objective_kkt.argtypes = [sp, i32, vp, vp, vp, dbl, i32, ctypes.POINTER(dbl),
+                                           ctypes.POINTER(dbl), vp]
+    lib.dicodile_dict_stats.argtypes = [sp, i32, vp, vp, vp, vp, vp]
+    for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
+              "dicodile_dict_stats"):
+        getattr(lib, f).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check(rc: int, allow_not_converged: bool = False) -> int:
+    if rc < 0 or (rc > 0 and not allow_not_converged):
+        msg = load().dicodile_last_error().decode(errors="replace")
+        raise DicodileError(rc, msg)
+    return rc
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float32:
+        return F32
+    if t.dtype == torch.float64:
+        return F64
+    raise DicodileError(-1, f"unsupported dtype {t.dtype} (float32 or float64)")
+
+
+def _device_tensor(t, name):
+    if not t.is_cuda:
+        raise DicodileError(-1, f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise DicodileError(-1, f"{name} must be contiguous")
+    return t
+
+
+def _shape(X, D) -> Shape:
+    s = Shape()
+    if X.dim() == 2 and D.dim() == 3:
+        s.ndim, s.P, s.K = 1, X.shape[0], D.shape[0]
+        s.T[0], s.L[0] = X.shape[1], D.shape[2]
+    elif X.dim() == 3 and D.dim() == 4:
+        s.ndim, s.P, s.K = 2, X.shape[0], D.shape[0]
+        s.T[0], s.T[1] = X.shape[1], X.shape[2]
+        s.L[0], s.L[1] = D.shape[2], D.shape[3]
+    else:
+        raise DicodileError(-1, f"unsupported shapes X{tuple(X.shape)} D{tuple(D.shape)}")
+    if D.shape[1] != X.shape[0]:
+        raise DicodileError(-1, "X and D disagree on the channel count P")
+    return s
+
+
+def _zshape(s: Shape):
+    if s.ndim == 1:
+        return (s.K, s.T[0] - s.L[0] + 1)
+    return (s.K, s.T[0] - s.L[0] + 1, s.T[1] - s.L[1] + 1)
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def dicodile_version() -> str:
+    return load().dicodile_version().decode()
+
+
+def dicodile_release() -> None:
+    _check(load().dicodile_release())
+
+
+def dicodile_dtd(D, stream=None):
+    """DtD (K, K, 2L-1[, 2L2-1]) of a device dictionary D (K, P, L...)."""
+    torch = _torch()
+    lib = load()
+    _device_tensor(D, "D")
+    s = Shape()
+    if D.dim() == 3:
+        s.ndim, s.K, s.P, s.T[0], s.L[0] = 1, D.shape[0], D.shape[1], D.shape[2], D.shape[2]
+        out = torch.empty((D.shape[0], D.shape[0], 2 * D.shape[2] - 1), dtype=D.dtype, device=D.device)
+    else:
+        s.ndim, s.K, s.P = 2, D.shape[0], D.shape[1]
+        s.T[0], s.T[1], s.L[0], s.L[1] = D.shape[2], D.shape[3], D.shape[2], D.shape[3]
+        out = torch.empty((D.shape[0], D.shape[0], 2 * D.shape[2] - 1, 2 * D.shape[3] - 1),
+                          dtype=D.dtype, device=D.device)
+    _check(lib.dicodile_dtd(ctypes.byref(s), _dtype_code(D), ctypes.c_void_p(D.data_ptr()),
+                            ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
+    lib = load()
+    _device_tensor(X, "X")
+    _device_tensor(D, "D")
+    s = _shape(X, D)
+    out = ctypes.c_double(0.0)
+    _check(lib.dicodile_lambda_max(ctypes.byref(s), _dtype_code(X), ctypes.c_void_p(X.data_ptr()),
+                                   ctypes.c_void_p(D.data_ptr()), int(positive), ctypes.byref(out),
+                                   _stream(stream)))
+    return out.value
+
+
+def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
+              tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
+              div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False) -> CscOpts:
+    o = CscOpts()
+    o.lambda_, o.tol = float(lam), float(tol)
+    o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
+    o.no_soft_lock, o.threads = int(no_soft_lock), int(threads)
+    if tile is not None:
+        t = (tile, 0) if isinstance(tile, int) else tuple(tile)
+        o.tile[0], o.tile[1] = int(t[0]), int(t[1])
+    if grid is not None:
+        g = (grid, 0) if isinstance(grid, int) else tuple(grid)
+        o.grid[0], o.grid[1] = int(g[0]), int(g[1])
+    o.warm_start, o.refresh_every, o.max_polish = int(warm_start), int(refresh_every), int(max_polish)
+    o.max_rounds, o.div_guard, o.timeout_s = int(max_rounds), float(div_guard), float(timeout_s)
+    o.kkt_target = float(kkt_target)
+    return o
+
+
+def info_dict(info: CscInfo, status: int) -> dict:
+    d = {f: getattr(info, f) for f, _ in CscInfo._fields_ if f != "reserved"}
+    d["grid"] = (info.grid[0], info.grid[1])
+    d["tile"] = (info.tile[0], info.tile[1])
+    d["status"] = STATUS.get(status, status)
+    return d
+
+
+def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
+    """Solve eq. csc on the device.  Returns (z, info dict).
+
+    Keyword options mirror dcdl_csc_opts: positive, certify, grid, tile,
+    threads, warm_start, refresh_every, max_polish, max_rounds, div_guard,
+    timeout_s, kkt_target, no_soft_lock.  A NOT_CONVERGED status is reported
+    in info['status']; errors raise DicodileError."""
+    torch = _torch()
+    lib = load()
+    _device_tensor(X, "X")
+    _device_tensor(D, "D")
+    s = _shape(X, D)
+    code = _dtype_code(X)
+    if D.dtype != X.dtype:
+        raise DicodileError(-1, "X and D must share a dtype")
+    if z_out is None:
+        if opts.get("warm_start"):
+            raise DicodileError(-1, "warm_start needs z_out")
+        z_out = torch.empty(_zshape(s), dtype=X.dtype, device=X.device)
+    _device_tensor(z_out, "z_out")
+    if tuple(z_out.shape) != _zshape(s) or z_out.dtype != X.dtype:
+        raise DicodileError(-1, f"z_out must be {_zshape(s)} {X.dtype}")
+    o = make_opts(lam, tol, code, **opts)
+    info = CscInfo()
+    rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(X.data_ptr()),
+                          ctypes.c_void_p(D.data_ptr()), ctypes.byref(o),
+                          ctypes.c_void_p(z_out.data_ptr()), ctypes.byref(info), _stream(stream))
+    _check(rc, allow_not_converged=True)
+    return z_out, info_dict(info, rc)
+
+
+def dicodile_objective_kkt(X, D, z, lam: float, positive: bool = False, stream=None):
+    """FP64 objective and strict KKT violation (/ lambda) of z."""
+    lib = load()
+    for t, n in ((X, "X"), (D, "D"), (z, "z")):
+        _device_tensor(t, n)
+    s = _shape(X, D)
+    obj, kkt = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    _check(lib.dicodile_objective_kkt(ctypes.byref(s), _dtype_code(X), ctypes.c_void_p(X.data_ptr()),
+                                      ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                      float(lam), int(positive), ctypes.byref(obj), ctypes.byref(kkt),
+                                      _stream(stream)))
+    return obj.value, kkt.value
+
+
+def dicodile_dict_stats(z, X, L, stream=None):
+    """(ztz, ztX) of eq. phi: ztz (K, K, 2L-1...), ztX (K, P, L...).  L is the
+    atom size: int for signals, (L1, L2) for images."""
+    torch = _torch()
+    lib = load()
+    _device_tensor(z, "z")
+    _device_tensor(X, "X")
+    s = Shape()
+    K, P = z.shape[0], X.shape[0]
+    if X.dim() == 2:
+        s.ndim, s.P, s.K, s.T[0], s.L[0] = 1, P, K, X.shape[1], int(L)
+        ztz = torch.empty((K, K, 2 * int(L) - 1), dtype=X.dtype, device=X.device)
+        ztX = torch.empty((K, P, int(L)), dtype=X.dtype, device=X.device)
+    else:
+        L1, L2 = int(L[0]), int(L[1])
+        s.ndim, s.P, s.K = 2, P, K
+        s.T[0], s.T[1], s.L[0], s.L[1] = X.shape[1], X.shape[2], L1, L2
+        ztz = torch.empty((K, K, 2 * L1 - 1, 2 * L2 - 1), dtype=X.dtype, device=X.device)
+        ztX = torch.empty((K, P, L1, L2), dtype=X.dtype, device=X.device)
+    if tuple(z.shape) != _zshape(s) or z.dtype != X.dtype:
+        raise DicodileError(-1, f"z must be {_zshape(s)} {X.dtype}")
+    _check(lib.dicodile_dict_stats(ctypes.byref(s), _dtype_code(X), ctypes.c_void_p(z.data_ptr()),
+                                   ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(ztz.data_ptr()),
+                                   ctypes.c_void_p(ztX.data_ptr()), _stream(stream)))
+    return ztz, ztX

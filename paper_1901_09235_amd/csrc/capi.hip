@@ -1,0 +1,812 @@
+// capi.hip -- host runtime and C ABI of the DiCoDiLe CSC library for gfx950.
+// The declarations, argument meanings, layouts and error behaviour are in
+// include/dicodile.h.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/dicodile.h"
+#include "dcdl_device.h"
+#include "dcdl_kernels.h"
+
+using namespace dcdl;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCK(expr)                                                                     \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess) return fail(DCDL_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// ------------------------------------------------------------- workspace
+struct Buf {
+  void *p = nullptr;
+  size_t n = 0;
+};
+
+struct DeviceState {
+  std::mutex mu;
+  std::map<std::string, Buf> bufs;
+  int cus = 0;
+  bool checked = false;
+  bool is_gfx950 = false;
+};
+
+std::mutex g_devices_mu;
+std::map<int, DeviceState *> g_devices;
+
+DeviceState *device_state(int *dev_out) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+  std::lock_guard<std::mutex> lk(g_devices_mu);
+  DeviceState *&s = g_devices[dev];
+  if (!s) s = new DeviceState();
+  if (dev_out) *dev_out = dev;
+  return s;
+}
+
+// Returns a device buffer of at least `bytes` bytes, reusing or growing the
+// named slot.  Synchronises `stream` before freeing an old allocation.
+int ws_get(DeviceState *ds, hipStream_t stream, const char *name, size_t bytes, void **out) {
+  if (bytes == 0) bytes = 256;
+  Buf &b = ds->bufs[name];
+  if (b.n < bytes) {
+    if (b.p) {
+      HIPCK(hipStreamSynchronize(stream));
+      HIPCK(hipFree(b.p));
+      b.p = nullptr;
+      b.n = 0;
+    }
+    size_t nb = bytes + bytes / 8;
+    if (hipMalloc(&b.p, nb) != hipSuccess) {
+      (void)hipGetLastError();
+      b.p = nullptr;
+      return fail(DCDL_ENOMEM, "workspace '%s': cannot allocate %zu bytes", name, nb);
+    }
+    b.n = nb;
+  }
+  *out = b.p;
+  return DCDL_OK;
+}
+
+#define WS(name, bytes, ptr)                                                              \
+  do {                                                                                    \
+    void *p_ = nullptr;                                                                   \
+    int rc_ = ws_get(ds, stream, name, (size_t)(bytes), &p_);                             \
+    if (rc_ != DCDL_OK) return rc_;                                                       \
+    ptr = reinterpret_cast<decltype(ptr)>(p_);                                            \
+  } while (0)
+
+int check_device(DeviceState *ds) {
+  if (!ds->checked) {
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIPCK(hipGetDeviceProperties(&prop, dev));
+    ds->is_gfx950 = std::strncmp(prop.gcnArchName, "gfx950", 6) == 0;
+    ds->cus = prop.multiProcessorCount;
+    ds->checked = true;
+  }
+  if (!ds->is_gfx950) return fail(DCDL_ENODEV, "the current device is not gfx950 (MI355X)");
+  return DCDL_OK;
+}
+
+// ------------------------------------------------------------- geometry
+int make_geom(const dcdl_shape *s, Geom *g) {
+  if (!s) return fail(DCDL_EINVAL, "shape is NULL");
+  if (s->ndim != 1 && s->ndim != 2) return fail(DCDL_EINVAL, "ndim must be 1 or 2 (got %d)", s->ndim);
+  if (s->P < 1 || s->K < 1 || s->K > 1024) return fail(DCDL_EINVAL, "need P >= 1 and 1 <= K <= 1024");
+  long long T1, T2;
+  int L1, L2;
+  if (s->ndim == 1) {
+    T1 = 1;
+    L1 = 1;
+    T2 = s->T[0];
+    L2 = s->L[0];
+  } else {
+    T1 = s->T[0];
+    T2 = s->T[1];
+    L1 = s->L[0];
+    L2 = s->L[1];
+  }
+  if (L1 < 1 || L2 < 1 || T1 < L1 || T2 < L2) return fail(DCDL_EINVAL, "need 1 <= L_i <= T_i");
+  if (T1 * T2 > (1ll << 31) - 1 || (T1 - L1 + 1) * (T2 - L2 + 1) * (long long)s->K > (1ll << 40))
+    return fail(DCDL_EINVAL, "problem too large for 32-bit position indices");
+  g->P = s->P;
+  g->K = s->K;
+  g->L1 = L1;
+  g->L2 = L2;
+  g->U1 = 2 * L1 - 1;
+  g->U2 = 2 * L2 - 1;
+  g->T1 = (int)T1;
+  g->T2 = (int)T2;
+  g->H = (int)(T1 - L1 + 1);
+  g->W = (int)(T2 - L2 + 1);
+  g->KS = s->K;
+  return DCDL_OK;
+}
+
+inline unsigned blocks_for(long long n, int nt) { return (unsigned)((n + nt - 1) / nt); }
+inline unsigned grid_stride_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  return (unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+
+// ------------------------------------------------------------- kernels
+template <class R>
+int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *dtd, R *A, R *inv_n) {
+  const size_t lds = 2 * sizeof(R) * (size_t)g.P * g.L1 * g.L2;
+  if (lds > 160 * 1024) return fail(DCDL_EINVAL, "atoms of %d values exceed the LDS budget", g.P * g.L1 * g.L2);
+  hipLaunchKernelGGL(dtd_kernel<R>, dim3(g.K * g.K), dim3(256), lds, stream, g, D, dtd, A, inv_n);
+  HIPCK(hipGetLastError());
+  return DCDL_OK;
+}
+
+template <class Rin, class Racc, class Rz, int MODE>
+int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, const CorrOut &o) {
+  constexpr int KC = sizeof(Racc) == 8 ? 8 : 16;
+  dim3 grid(blocks_for(g.W, 32), blocks_for(g.H, 8));
+  const size_t lds = sizeof(Racc) * (size_t)g.L2 * KC;
+  hipLaunchKernelGGL((corr_kernel<Rin, Racc, Rz, MODE, KC>), grid, dim3(256), lds, stream, g, X, D, o);
+  HIPCK(hipGetLastError());
+  return DCDL_OK;
+}
+
+// FP64 residual res = X - Z*D from a position-major z; returns nnz and sum|z|.
+template <class R>
+int residual64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const double *D64, const R *zpm,
+               double **res_out, long long *nnz_out, double *l1_out) {
+  const long long nx = (long long)g.P * g.T1 * g.T2, nz = (long long)g.H * g.W * g.KS;
+  double *res;
+  unsigned long long *cnt;
+  double *l1;
+  WS("res64", sizeof(double) * nx, res);
+  WS("nzcount", 64, cnt);
+  l1 = reinterpret_cast<double *>(cnt + 1);
+  hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, res);
+  HIPCK(hipMemsetAsync(cnt, 0, 16, stream));
+  hipLaunchKernelGGL(collect_nonzeros<R>, dim3(grid_stride_blocks(nz)), dim3(256), 0, stream, nz, g.KS, zpm, cnt,
+                     (NzEntry *)nullptr, 0ull, l1);
+  HIPCK(hipGetLastError());
+  unsigned long long hc[2];
+  HIPCK(hipMemcpyAsync(hc, cnt, 16, hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  const unsigned long long n = hc[0];
+  double l1v;
+  std::memcpy(&l1v, &hc[1], sizeof(double));
+  if (n > 0) {
+    NzEntry *list;
+    WS("nzlist", sizeof(NzEntry) * n, list);
+    HIPCK(hipMemsetAsync(cnt, 0, 8, stream));
+    hipLaunchKernelGGL(collect_nonzeros<R>, dim3(grid_stride_blocks(nz)), dim3(256), 0, stream, nz, g.KS, zpm, cnt,
+                       list, n, (double *)nullptr);
+    const long long nb = (long long)n < 65536 ? (long long)n : 65536;
+    hipLaunchKernelGGL(scatter_atoms<double>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, (long long)n, D64,
+                       res);
+    HIPCK(hipGetLastError());
+  }
+  *res_out = res;
+  *nnz_out = (long long)n;
+  *l1_out = l1v;
+  return DCDL_OK;
+}
+
+// FP64 objective and strict KKT of a position-major z.  Leaves the FP64
+// residual in the "res64" slot and D in FP64 in the "D64" slot.
+template <class R>
+int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
+            int positive, double *obj, double *kkt, long long *nnz) {
+  const long long nd = (long long)g.K * g.P * g.L1 * g.L2;
+  double *D64, *res, *scal;
+  WS("D64", sizeof(double) * nd, D64);
+  WS("scal", 64, scal);
+  hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
+  long long n = 0;
+  double l1 = 0;
+  int rc = residual64<R>(ds, stream, g, X, D64, zpm, &res, &n, &l1);
+  if (rc) return rc;
+  HIPCK(hipMemsetAsync(scal, 0, 16, stream));
+  const long long nx = (long long)g.P * g.T1 * g.T2;
+  hipLaunchKernelGGL(sum_squares, dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res, scal);
+  CorrOut o{};
+  o.zpm = zpm;
+  o.lambda = lambda;
+  o.positive = positive;
+  o.result = scal + 1;
+  rc = run_corr<double, double, R, CORR_KKT>(stream, g, res, D64, o);
+  if (rc) return rc;
+  double h[2];
+  HIPCK(hipMemcpyAsync(h, scal, 16, hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  if (obj) *obj = 0.5 * h[0] + lambda * l1;
+  if (kkt) *kkt = h[1] / lambda;
+  if (nnz) *nnz = n;
+  return DCDL_OK;
+}
+
+// beta = corr(X - Z*D, D) + n z by an FP64 contraction, rounded to R: the
+// definition of beta in Sec. 3, used for warm starts and drift correction.
+// With fresh = false it reuses the residual and D64 left by check64.
+template <class R>
+int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
+                  const double *nrm64, R *beta, bool fresh) {
+  const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
+  double *D64, *res;
+  WS("D64", sizeof(double) * nd, D64);
+  if (fresh) {
+    hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
+    long long n = 0;
+    double l1 = 0;
+    int rc = residual64<R>(ds, stream, g, X, D64, zpm, &res, &n, &l1);
+    if (rc) return rc;
+  } else {
+    WS("res64", sizeof(double) * nx, res);
+  }
+  CorrOut ob{};
+  ob.beta = beta;
+  ob.zpm = zpm;
+  ob.nrm = nrm64;
+  return run_corr<double, double, R, CORR_BETA>(stream, g, res, D64, ob);
+}
+
+// Exact FP64 norms from D.
+template <class R>
+__global__ void norms64(int K, int PL, const R *D, double *nrm) {
+  __shared__ double sh[4];
+  const int k = blockIdx.x;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < PL; i += blockDim.x) {
+    const double d = (double)D[(long long)k * PL + i];
+    a += d * d;
+  }
+  a = block_sum<256>(a, sh);
+  if (threadIdx.x == 0) nrm[k] = a;
+}
+
+// ------------------------------------------------------------- grid plan
+struct Plan {
+  int W1, W2, tile1, tile2, mmax, nt;
+};
+
+template <class R, int NT>
+int capacity(DeviceState *ds, int *cap) {
+  int nb = 0;
+  HIPCK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(lgcd_rounds<R, NT>), NT, 0));
+  *cap = nb * ds->cus;
+  return DCDL_OK;
+}
+
+int plan_grid(const Geom &g, int ndim, const dcdl_csc_opts *o, int cap, Plan *p) {
+  p->tile1 = o->tile[0] > 0 ? o->tile[0] : (ndim == 1 ? 1 : 2 * g.L1);
+  p->tile2 = o->tile[1] > 0 ? o->tile[1] : 2 * g.L2;
+  if (ndim == 1 && o->tile[0] <= 0 && o->tile[1] <= 0) {
+    p->tile1 = 1;
+    p->tile2 = 2 * g.L2;
+  }
+  if (ndim == 1 && o->tile[0] > 0 && o->tile[1] <= 0) {  // 1-D: tile[0] is the length
+    p->tile2 = o->tile[0];
+    p->tile1 = 1;
+  }
+  const int max1 = g.H / g.L1 > 0 ? g.H / g.L1 : 1, max2 = g.W / g.L2 > 0 ? g.W / g.L2 : 1;
+  int W1, W2;
+  if (o->grid[0] > 0 || o->grid[1] > 0) {
+    W1 = ndim == 1 ? 1 : (o->grid[0] > 0 ? o->grid[0] : 1);
+    W2 = ndim == 1 ? (o->grid[0] > 0 ? o->grid[0] : o->grid[1]) : (o->grid[1] > 0 ? o->grid[1] : 1);
+    if (W1 > max1 && W1 > 1) return fail(DCDL_EINVAL, "grid[0]=%d leaves workers shorter than L1=%d", W1, g.L1);
+    if (W2 > max2 && W2 > 1) return fail(DCDL_EINVAL, "grid=%d leaves workers shorter than L=%d", W2, g.L2);
+    if (W1 > g.H || W2 > g.W) return fail(DCDL_EINVAL, "more workers than positions");
+  } else {
+    W1 = std::max(1, std::min(g.H / p->tile1, max1));
+    W2 = std::max(1, std::min(g.W / p->tile2, max2));
+    if ((long long)W1 * W2 > cap) {
+      const double f = std::sqrt((double)cap / ((double)W1 * W2));
+      if (ndim == 1) {
+        W2 = std::max(1, cap);
+      } else {
+        W1 = std::max(1, (int)(W1 * f));
+        W2 = std::max(1, (int)(W2 * f));
+        while ((long long)W1 * W2 > cap) {
+          if (W1 >= W2) --W1; else --W2;
+        }
+      }
+    }
+  }
+  if ((long long)W1 * W2 > cap)
+    return fail(DCDL_EINVAL, "worker grid %dx%d exceeds the %d co-resident workgroups", W1, W2, cap);
+  const int ext1 = (g.H + W1 - 1) / W1, ext2 = (g.W + W2 - 1) / W2;
+  p->W1 = W1;
+  p->W2 = W2;
+  p->mmax = ((ext1 + p->tile1 - 1) / p->tile1) * ((ext2 + p->tile2 - 1) / p->tile2);
+  return DCDL_OK;
+}
+
+template <class R>
+int launch_rounds(hipStream_t stream, int nt, Inst<R> *d_inst, int *d_wg, int nwg, long long timeout_ticks) {
+  void *args[] = {&d_inst, &d_wg, &timeout_ticks};
+  const void *fn;
+  switch (nt) {
+    case 64: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 64>); break;
+    case 128: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 128>); break;
+    case 512: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 512>); break;
+    case 1024: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 1024>); break;
+    default: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 256>); break;
+  }
+  HIPCK(hipLaunchCooperativeKernel(fn, dim3(nwg), dim3(nt), args, 0, stream));
+  return DCDL_OK;
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------- the solve
+template <class R>
+int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, const R *X, const R *D,
+             const dcdl_csc_opts *o, R *z_out, dcdl_csc_info *info) {
+  const double t_start = now_s();
+  Geom g = g_user;
+  g.KS = atom_stride(g.K, (int)sizeof(R));
+  const long long HW = (long long)g.H * g.W, nz = HW * g.KS;
+  const long long nA = (long long)g.K * g.U1 * g.U2 * g.KS;
+  const int nt = (o->threads == 64 || o->threads == 128 || o->threads == 512 || o->threads == 1024) ? o->threads : 256;
+  int cap = 0, rc;
+  if (nt == 64) rc = capacity<R, 64>(ds, &cap);
+  else if (nt == 128) rc = capacity<R, 128>(ds, &cap);
+  else if (nt == 512) rc = capacity<R, 512>(ds, &cap);
+  else if (nt == 1024) rc = capacity<R, 1024>(ds, &cap);
+  else rc = capacity<R, 256>(ds, &cap);
+  if (rc) return rc;
+  Plan pl;
+  if ((rc = plan_grid(g, ndim, o, cap, &pl))) return rc;
+  const int nW = pl.W1 * pl.W2;
+
+  R *beta, *zpm, *A, *dtd, *inv_n, *score;
+  uint32_t *meta;
+  double *nrm64;
+  unsigned long long *cand;
+  int *prog, *wg;
+  Ctl *ctl;
+  Inst<R> *d_inst;
+  WS("beta", sizeof(R) * nz, beta);
+  WS("zpm", sizeof(R) * nz, zpm);
+  WS("score", sizeof(R) * HW, score);
+  WS("meta", sizeof(uint32_t) * HW, meta);
+  WS("applyA", sizeof(R) * nA, A);
+  WS("dtd", sizeof(R) * (size_t)g.K * g.K * g.U1 * g.U2, dtd);
+  WS("inv_n", sizeof(R) * g.KS, inv_n);
+  WS("nrm64", sizeof(double) * g.K, nrm64);
+  WS("cand", sizeof(unsigned long long) * 2 * nW, cand);
+  WS("prog", sizeof(int) * nW, prog);
+  WS("wg", sizeof(int) * nW, wg);
+  WS("ctl", sizeof(Ctl) + sizeof(int) * 2 * kRing, ctl);
+  WS("inst", sizeof(Inst<R>), d_inst);
+
+  hipEvent_t ev0, ev1, ev2;
+  HIPCK(hipEventCreate(&ev0));
+  HIPCK(hipEventCreate(&ev1));
+  HIPCK(hipEventCreate(&ev2));
+  HIPCK(hipEventRecord(ev0, stream));
+  if (g.KS != g.K) HIPCK(hipMemsetAsync(A, 0, sizeof(R) * nA, stream));  // padding atoms patch nothing
+  HIPCK(hipMemsetAsync(inv_n, 0, sizeof(R) * g.KS, stream));
+  if ((rc = run_dtd<R>(ds, stream, g, D, dtd, A, inv_n))) return rc;
+  hipLaunchKernelGGL(norms64<R>, dim3(g.K), dim3(256), 0, stream, g.K, g.P * g.L1 * g.L2, D, nrm64);
+  const unsigned pb = blocks_for(HW, 256);
+  if (o->warm_start) {
+    hipLaunchKernelGGL((to_position_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, z_out, zpm);
+    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
+  } else {
+    HIPCK(hipMemsetAsync(zpm, 0, sizeof(R) * nz, stream));
+    CorrOut ob{};
+    ob.beta = beta;
+    if ((rc = run_corr<R, R, R, CORR_BETA>(stream, g, X, D, ob))) return rc;
+  }
+  const R lam = (R)o->lambda, tol = (R)o->tol;
+  hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam, tol,
+                     o->positive, o->certify, score, meta);
+  HIPCK(hipGetLastError());
+  HIPCK(hipEventRecord(ev1, stream));
+  HIPCK(hipEventSynchronize(ev1));
+  float ms_init = 0;
+  HIPCK(hipEventElapsedTime(&ms_init, ev0, ev1));
+
+  Inst<R> hi{};
+  hi.K = g.K;
+  hi.KS = g.KS;
+  hi.L1 = g.L1;
+  hi.L2 = g.L2;
+  hi.U1 = g.U1;
+  hi.U2 = g.U2;
+  hi.H = g.H;
+  hi.W = g.W;
+  hi.W1 = pl.W1;
+  hi.W2 = pl.W2;
+  hi.tile1 = pl.tile1;
+  hi.tile2 = pl.tile2;
+  hi.mmax = pl.mmax;
+  hi.wg_base = 0;
+  hi.positive = o->positive;
+  hi.certify = o->certify;
+  hi.soft_lock = o->no_soft_lock ? 0 : 1;
+  hi.lambda = lam;
+  hi.tol = tol;
+  hi.div_guard = (R)o->div_guard;
+  hi.beta = beta;
+  hi.z = zpm;
+  hi.score = score;
+  hi.meta = meta;
+  hi.A = A;
+  hi.inv_n = inv_n;
+  hi.cand = cand;
+  hi.prog = prog;
+  hi.ctl = ctl;
+  hi.ring = reinterpret_cast<int *>(ctl + 1);
+  HIPCK(hipMemsetAsync(wg, 0, sizeof(int) * nW, stream));
+
+  const double kkt_target = o->kkt_target > 0 ? o->kkt_target : 1e-4;
+  const int max_polish = o->max_polish > 0 ? o->max_polish : 2;
+  const int refresh = o->refresh_every > 0 ? o->refresh_every : 0;
+  long long rounds_left = o->max_rounds > 0 ? o->max_rounds : (1ll << 30);
+  double t_cd = 0, t_check = 0, obj = 0, kkt = 0;
+  long long nnz = 0;
+  unsigned long long upd = 0, cands = 0, locked = 0, visits = 0, checked = 0, patched = 0;
+  double tw_wait = 0, tw_sel = 0, tw_col = 0, tw_app = 0;
+  long long rounds = 0, sweeps = 0;
+  int passes = 0, status = DCDL_NOT_CONVERGED, converged = 0;
+  const long long timeout_ticks = 500000000ll;  // 5 s per neighbour wait, 100 MHz clock
+  for (;;) {
+    ++passes;
+    long long chunk = refresh > 0 ? (long long)refresh * pl.mmax : rounds_left;
+    if (chunk > rounds_left) chunk = rounds_left;
+    if (chunk > (1ll << 22) - 2) chunk = (1ll << 22) - 2;  // candidate tags hold 22 bits of round
+    hi.max_rounds = chunk;
+    {
+      double budget = 120.0;  // per launch unless the caller asks for less
+      if (o->timeout_s > 0) budget = std::max(1e-3, o->timeout_s - (now_s() - t_start));
+      hi.budget_ticks = (long long)(budget * 1e8);
+    }
+    HIPCK(hipMemcpyAsync(d_inst, &hi, sizeof(hi), hipMemcpyHostToDevice, stream));
+    HIPCK(hipMemsetAsync(prog, 0, sizeof(int) * nW, stream));
+    // all-ones tags carry a round number no launch reaches
+    HIPCK(hipMemsetAsync(cand, 0xff, sizeof(unsigned long long) * 2 * nW, stream));
+    HIPCK(hipMemsetAsync(ctl, 0, sizeof(Ctl) + sizeof(int) * 2 * kRing, stream));
+    HIPCK(hipEventRecord(ev1, stream));
+    if ((rc = launch_rounds<R>(stream, nt, d_inst, wg, nW, timeout_ticks))) return rc;
+    HIPCK(hipEventRecord(ev2, stream));
+    Ctl hc;
+    HIPCK(hipMemcpyAsync(&hc, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, stream));
+    HIPCK(hipStreamSynchronize(stream));
+    float ms = 0;
+    HIPCK(hipEventElapsedTime(&ms, ev1, ev2));
+    t_cd += ms * 1e-3;
+    upd += hc.n_updates;
+    cands += hc.n_candidates;
+    locked += hc.n_softlocked;
+    visits += hc.n_visits;
+    checked += hc.n_checked;
+    patched += hc.n_patched;
+    tw_wait += hc.tk_wait * 1e-8 / nW;
+    tw_sel += hc.tk_select * 1e-8 / nW;
+    tw_col += hc.tk_collect * 1e-8 / nW;
+    tw_app += hc.tk_apply * 1e-8 / nW;
+    rounds += hc.max_round;
+    sweeps += hc.sweeps_done;
+    rounds_left -= hc.max_round;
+    if (hc.status == 2) {
+      status = fail(DCDL_EDIVERGED, "divergence guard tripped (|z| > %g)", o->div_guard);
+      break;
+    }
+    if (hc.status == 3) {
+      status = fail(DCDL_ETIMEOUT, "a worker waited on a neighbour for more than 5 s");
+      break;
+    }
+    const bool time_capped = hc.status == 4;
+    const double tc0 = now_s();
+    const bool sweep_done = hc.converged != 0;
+    // FP64 check of the iterate (objective, strict KKT)
+    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz);
+    if (rc) return rc;
+    if (sweep_done && kkt <= kkt_target) {
+      t_check += now_s() - tc0;
+      converged = 1;
+      status = DCDL_OK;
+      break;
+    }
+    if (rounds_left <= 0 || time_capped || (o->timeout_s > 0 && now_s() - t_start > o->timeout_s) ||
+        (sweep_done && passes >= 1 + max_polish)) {
+      t_check += now_s() - tc0;
+      break;
+    }
+    // another pass: beta from its definition (FP64 drift correction)
+    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, false))) return rc;
+    hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam,
+                       tol, o->positive, o->certify, score, meta);
+    HIPCK(hipStreamSynchronize(stream));
+    t_check += now_s() - tc0;
+  }
+  hipLaunchKernelGGL((to_atom_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, zpm, z_out);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(stream));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  (void)hipEventDestroy(ev2);
+  if (info) {
+    std::memset(info, 0, sizeof(*info));
+    info->n_updates = (long long)upd;
+    info->n_candidates = (long long)cands;
+    info->n_softlocked = (long long)locked;
+    info->n_rounds = rounds;
+    info->n_sweeps = sweeps;
+    info->n_nonzero = nnz;
+    info->objective = obj;
+    info->kkt = kkt;
+    info->lambda_max = std::nan("");
+    info->t_total_s = now_s() - t_start;
+    info->t_init_s = ms_init * 1e-3;
+    info->t_cd_s = t_cd;
+    info->t_check_s = t_check;
+    info->converged = converged;
+    info->grid[0] = pl.W1;
+    info->grid[1] = pl.W2;
+    info->tile[0] = pl.tile1;
+    info->tile[1] = pl.tile2;
+    info->n_passes = passes;
+    info->n_visits = (long long)visits;
+    info->n_checked = (long long)checked;
+    info->n_patched = (long long)patched;
+    info->t_worker_wait_s = tw_wait;
+    info->t_worker_select_s = tw_sel;
+    info->t_worker_collect_s = tw_col;
+    info->t_worker_apply_s = tw_app;
+  }
+  return status;
+}
+
+struct Guard {
+  DeviceState *ds;
+  explicit Guard(DeviceState *d) : ds(d) { ds->mu.lock(); }
+  ~Guard() { ds->mu.unlock(); }
+};
+
+#define PROLOGUE()                                                        \
+  g_err.clear();                                                          \
+  DeviceState *ds = device_state(nullptr);                                \
+  if (!ds) return fail(DCDL_EHIP, "hipGetDevice failed");                 \
+  Guard guard_(ds);                                                       \
+  {                                                                       \
+    int rc0_ = check_device(ds);                                          \
+    if (rc0_) return rc0_;                                                \
+  }                                                                       \
+  hipStream_t stream = reinterpret_cast<hipStream_t>(stream_);
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+const char *dicodile_version(void) { return "dicodile-mi355x 0.1 (gfx950)"; }
+
+const char *dicodile_last_error(void) { return g_err.c_str(); }
+
+int dicodile_release(void) {
+  g_err.clear();
+  DeviceState *ds = device_state(nullptr);
+  if (!ds) return fail(DCDL_EHIP, "hipGetDevice failed");
+  Guard guard_(ds);
+  HIPCK(hipDeviceSynchronize());
+  for (auto &kv : ds->bufs)
+    if (kv.second.p) HIPCK(hipFree(kv.second.p));
+  ds->bufs.clear();
+  return DCDL_OK;
+}
+
+int dicodile_dtd(const dcdl_shape *shape, dcdl_dtype dtype, const void *D, void *dtd_out, void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!D || !dtd_out) return fail(DCDL_EINVAL, "NULL pointer");
+  PROLOGUE();
+  const long long nA = (long long)g.K * g.U1 * g.U2 * g.K;
+  if (dtype == DCDL_F32) {
+    float *A, *inv;
+    WS("applyA", sizeof(float) * nA, A);
+    WS("inv_n", sizeof(float) * g.K, inv);
+    if ((rc = run_dtd<float>(ds, stream, g, (const float *)D, (float *)dtd_out, A, inv))) return rc;
+  } else if (dtype == DCDL_F64) {
+    double *A, *inv;
+    WS("applyA", sizeof(double) * nA, A);
+    WS("inv_n", sizeof(double) * g.K, inv);
+    if ((rc = run_dtd<double>(ds, stream, g, (const double *)D, (double *)dtd_out, A, inv))) return rc;
+  } else {
+    return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
+  }
+  HIPCK(hipStreamSynchronize(stream));
+  return DCDL_OK;
+}
+
+int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D, int32_t positive,
+                        double *out, void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!X || !D || !out) return fail(DCDL_EINVAL, "NULL pointer");
+  if (dtype != DCDL_F32 && dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
+  PROLOGUE();
+  const long long nx = (long long)g.P * g.T1 * g.T2, nd = (long long)g.K * g.P * g.L1 * g.L2;
+  double *X64, *D64, *scal;
+  WS("res64", sizeof(double) * nx, X64);
+  WS("D64", sizeof(double) * nd, D64);
+  WS("scal", 64, scal);
+  if (dtype == DCDL_F32) {
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx,
+                       (const float *)X, X64);
+    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd,
+                       (const float *)D, D64);
+  } else {
+    HIPCK(hipMemcpyAsync(X64, X, sizeof(double) * nx, hipMemcpyDeviceToDevice, stream));
+    HIPCK(hipMemcpyAsync(D64, D, sizeof(double) * nd, hipMemcpyDeviceToDevice, stream));
+  }
+  HIPCK(hipMemsetAsync(scal, 0, 16, stream));
+  CorrOut o{};
+  o.positive = positive;
+  o.result = scal;
+  if ((rc = run_corr<double, double, double, CORR_ABSMAX>(stream, g, X64, D64, o))) return rc;
+  HIPCK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  return DCDL_OK;
+}
+
+int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dcdl_csc_opts *opts, void *z_out,
+                 dcdl_csc_info *info, void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!X || !D || !opts || !z_out) return fail(DCDL_EINVAL, "NULL pointer");
+  if (!(opts->lambda > 0)) return fail(DCDL_EINVAL, "lambda must be > 0");
+  if (!(opts->tol >= 0)) return fail(DCDL_EINVAL, "tol must be >= 0");
+  if (opts->dtype != DCDL_F32 && opts->dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype");
+  if (opts->threads != 0 && opts->threads != 64 && opts->threads != 128 && opts->threads != 256 &&
+      opts->threads != 512 && opts->threads != 1024)
+    return fail(DCDL_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
+  if (opts->tile[0] < 0 || opts->tile[1] < 0 || opts->grid[0] < 0 || opts->grid[1] < 0)
+    return fail(DCDL_EINVAL, "negative tile or grid");
+  if (opts->max_rounds > (1ll << 30)) return fail(DCDL_EINVAL, "max_rounds above 2^30");
+  PROLOGUE();
+  if (opts->dtype == DCDL_F32)
+    return csc_impl<float>(ds, stream, g, shape->ndim, (const float *)X, (const float *)D, opts, (float *)z_out, info);
+  return csc_impl<double>(ds, stream, g, shape->ndim, (const double *)X, (const double *)D, opts, (double *)z_out,
+                          info);
+}
+
+int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D, const void *z,
+                           double lambda, int32_t positive, double *objective, double *kkt, void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!X || !D || !z) return fail(DCDL_EINVAL, "NULL pointer");
+  if (!(lambda > 0)) return fail(DCDL_EINVAL, "lambda must be > 0");
+  PROLOGUE();
+  const long long HW = (long long)g.H * g.W, nz = HW * g.K;
+  const unsigned pb = blocks_for(HW, 256);
+  if (dtype == DCDL_F32) {
+    float *zpm;
+    WS("zpm_check", sizeof(float) * nz, zpm);
+    hipLaunchKernelGGL((to_position_major<float, float>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS,
+                       (const float *)z, zpm);
+    return check64<float>(ds, stream, g, (const float *)X, (const float *)D, zpm, lambda, positive, objective, kkt,
+                          nullptr);
+  } else if (dtype == DCDL_F64) {
+    double *zpm;
+    WS("zpm_check", sizeof(double) * nz, zpm);
+    hipLaunchKernelGGL((to_position_major<double, double>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS,
+                       (const double *)z, zpm);
+    return check64<double>(ds, stream, g, (const double *)X, (const double *)D, zpm, lambda, positive, objective,
+                           kkt, nullptr);
+  }
+  return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
+}
+
+}  // extern "C"
+
+namespace {
+
+template <class R>
+int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R *z, const R *X, R *ztz, R *ztX) {
+  const long long HW = (long long)g.H * g.W, nz = HW * g.K;
+  const long long nphi = (long long)g.K * g.K * g.U1 * g.U2, npsi = (long long)g.K * g.P * g.L1 * g.L2;
+  unsigned int *cnt;
+  double *phi64, *psi64;
+  R *zpm;
+  int *nzc;
+  WS("st_cnt", sizeof(unsigned int) * 2 * g.K, cnt);
+  WS("st_phi", sizeof(double) * nphi, phi64);
+  WS("st_psi", sizeof(double) * npsi, psi64);
+  WS("st_zpm", sizeof(R) * nz, zpm);
+  WS("st_nzc", sizeof(int) * HW, nzc);
+  HIPCK(hipMemsetAsync(cnt, 0, sizeof(unsigned int) * 2 * g.K, stream));
+  HIPCK(hipMemsetAsync(phi64, 0, sizeof(double) * nphi, stream));
+  HIPCK(hipMemsetAsync(psi64, 0, sizeof(double) * npsi, stream));
+  const unsigned gx = (unsigned)std::min<long long>(blocks_for(HW, 256), 1024);
+  hipLaunchKernelGGL(count_per_atom<R>, dim3(gx, g.K), dim3(256), 0, stream, (int)HW, g.K, z, cnt);
+  std::vector<unsigned int> hc(g.K);
+  HIPCK(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned int) * g.K, hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  std::vector<unsigned int> off(g.K);
+  long long total = 0;
+  std::vector<Chunk> chunks;
+  constexpr int CH = 128;
+  for (int k = 0; k < g.K; ++k) {
+    off[k] = (unsigned int)total;
+    for (unsigned int b = 0; b < hc[k]; b += CH) {
+      Chunk c;
+      c.k = k;
+      c.beg = (int)(total + b);
+      c.end = (int)(total + std::min<unsigned int>(hc[k], b + CH));
+      c.pad = 0;
+      chunks.push_back(c);
+    }
+    total += hc[k];
+  }
+  if (total > 0) {
+    NzEntry *list;
+    Chunk *d_chunks;
+    WS("st_list", sizeof(NzEntry) * total, list);
+    WS("st_chunks", sizeof(Chunk) * chunks.size(), d_chunks);
+    HIPCK(hipMemcpyAsync(cnt + g.K, off.data(), sizeof(unsigned int) * g.K, hipMemcpyHostToDevice, stream));
+    HIPCK(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, stream));
+    hipLaunchKernelGGL(list_per_atom<R>, dim3(gx, g.K), dim3(256), 0, stream, (int)HW, g.K, z, cnt + g.K, list);
+    const unsigned pb = blocks_for(HW, 256);
+    hipLaunchKernelGGL((to_position_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, z, zpm);
+    hipLaunchKernelGGL(count_per_position<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, zpm, nzc);
+    hipLaunchKernelGGL(psi_kernel<R>, dim3((unsigned)chunks.size()), dim3(256), 0, stream, g, d_chunks, list, X,
+                       psi64);
+    const long long nb = total < 65536 ? total : 65536;
+    hipLaunchKernelGGL(phi_kernel<R>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, total, zpm, nzc, phi64);
+    HIPCK(hipGetLastError());
+  }
+  hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(nphi)), dim3(256), 0, stream, nphi, phi64,
+                     ztz);
+  hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(npsi)), dim3(256), 0, stream, npsi, psi64,
+                     ztX);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(stream));
+  return DCDL_OK;
+}
+
+}  // namespace
+
+extern "C" int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, const void *z, const void *X,
+                                   void *ztz_out, void *ztX_out, void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!z || !X || !ztz_out || !ztX_out) return fail(DCDL_EINVAL, "NULL pointer");
+  PROLOGUE();
+  if (dtype == DCDL_F32)
+    return dict_stats_impl<float>(ds, stream, g, (const float *)z, (const float *)X, (float *)ztz_out,
+                                  (float *)ztX_out);
+  if (dtype == DCDL_F64)
+    return dict_stats_impl<double>(ds, stream, g, (const double *)z, (const double *)X, (double *)ztz_out,
+                                   (double *)ztX_out);
+  return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
+}

@@ -1,0 +1,654 @@
+// dcdl_device.h -- gfx950 device code of the DiCoDiLe CSC library.
+//
+// Internal layout (all on the device):
+//   beta, z : position-major (H, W, KS), the atom index innermost and padded
+//             to KS = K rounded up to a 16-byte vector (4 floats or 2 doubles;
+//             padding entries stay 0).  The beta patch of one update (Sec. 3,
+//             eq. beta_update) is (2L1-1) contiguous, 16-byte aligned runs of
+//             (2L2-1)*KS values, read and written as vectors.
+//   score   : per position, the best move score over its K atoms (Alg. 1's
+//             selection key); read by neighbouring workers, so it is accessed
+//             with coherent atomics.
+//   meta    : per position, the atom of that best move (low 16 bits) and the
+//             number of non-zero atoms (high 16 bits); private to the owner.
+//   A       : apply table A[k0][d1][d2][k] = DtD[k][k0][d1][d2] (k padded to KS):
+//             the row of eq. beta_update for an update of atom k0, indexed by
+//             the offset d = w - w0 + L - 1 of the patched position w.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dcdl {
+
+template <class R> struct Vec;
+template <> struct Vec<float> {
+  typedef float4 T;
+  static constexpr int N = 4;
+  static __device__ __forceinline__ float get(const float4 &v, int e) {
+    return e == 0 ? v.x : e == 1 ? v.y : e == 2 ? v.z : v.w;
+  }
+  static __device__ __forceinline__ float4 fma_neg(float4 b, float4 a, float d) {
+    return make_float4(b.x - a.x * d, b.y - a.y * d, b.z - a.z * d, b.w - a.w * d);
+  }
+  static __device__ __forceinline__ float4 zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+  static __device__ __forceinline__ void set(float4 &v, int e, float x) {
+    if (e == 0) v.x = x;
+    else if (e == 1) v.y = x;
+    else if (e == 2) v.z = x;
+    else v.w = x;
+  }
+};
+template <> struct Vec<double> {
+  typedef double2 T;
+  static constexpr int N = 2;
+  static __device__ __forceinline__ double get(const double2 &v, int e) { return e == 0 ? v.x : v.y; }
+  static __device__ __forceinline__ double2 fma_neg(double2 b, double2 a, double d) {
+    return make_double2(b.x - a.x * d, b.y - a.y * d);
+  }
+  static __device__ __forceinline__ double2 zero() { return make_double2(0.0, 0.0); }
+  static __device__ __forceinline__ void set(double2 &v, int e, double x) {
+    if (e == 0) v.x = x;
+    else v.y = x;
+  }
+};
+
+// Padded atom stride: K rounded up to a whole vector.
+__host__ __device__ inline int atom_stride(int K, int elem_bytes) {
+  const int ve = 16 / elem_bytes;
+  return (K + ve - 1) / ve * ve;
+}
+
+// Per-instance control block, followed in memory by two rings of kRing ints
+// (sweep completion counts and sweep activity flags).
+struct Ctl {
+  int32_t converged;
+  int32_t stop;
+  int32_t status;  // 0 ok, 1 round cap, 2 diverged, 3 neighbour wait timed out
+  int32_t max_round;
+  int32_t sweeps_done;
+  int32_t pad[3];
+  unsigned long long n_updates, n_candidates, n_softlocked;
+  unsigned long long n_visits;        // rounds in which a worker scanned a sub-domain
+  unsigned long long n_checked;       // positions read by soft-lock tests
+  unsigned long long n_patched;       // positions of beta patched (summed over workers)
+  unsigned long long tk_wait, tk_select, tk_collect, tk_apply;  // clock ticks summed over workers
+};
+constexpr int kRing = 4096;
+
+// Everything one instance of eq. csc needs inside the round kernel.
+template <class R> struct Inst {
+  int K, KS, L1, L2, U1, U2;
+  int H, W;
+  int W1, W2, tile1, tile2, mmax, wg_base;
+  int positive, certify, soft_lock, pad0;
+  R lambda, tol, div_guard;
+  long long max_rounds;
+  long long budget_ticks;  // wall-clock cap of one launch, 100 MHz clock ticks
+  R *beta, *z;
+  R *score;        // shared: coherent accesses only
+  uint32_t *meta;  // private to the owning worker
+  const R *A, *inv_n;
+  unsigned long long *cand;  // 2 words per worker
+  int *prog;
+  Ctl *ctl;
+  int *ring;  // done[kRing] then active[kRing]
+};
+
+// ----------------------------------------------------------------- arithmetic
+
+// Closed-form coordinate target of eq. pb_coord: ST(b, lambda) / ||D_k||^2,
+// one-sided when positive.
+template <class R>
+__device__ __forceinline__ R st_target(R b, R lam, R inv_n, int positive) {
+  R u;
+  if (positive)
+    u = b > lam ? b - lam : R(0);
+  else
+    u = b > lam ? b - lam : (b < -lam ? b + lam : R(0));
+  return u * inv_n;
+}
+
+// Selection score of the move z -> zn: |zn - z|, raised to at least tol for a
+// move that changes the support or the sign when certify is set.
+template <class R>
+__device__ __forceinline__ R move_score(R z, R zn, R tol, int certify) {
+  R dz = zn > z ? zn - z : z - zn;
+  if (certify && z != R(0) && (zn == R(0) || ((zn > R(0)) != (z > R(0)))))
+    dz = dz > tol ? dz : tol;
+  return dz;
+}
+
+__device__ __forceinline__ int part_start(int j, int N, int Wn) {
+  return (int)(((long long)j * N) / Wn);
+}
+__device__ __forceinline__ int part_owner(int x, int N, int Wn) {
+  return (int)((((long long)x + 1) * Wn - 1) / N);
+}
+
+// ------------------------------------------------------------ synchronisation
+//
+// Workers exchange three kinds of data: the cached best move of positions on
+// their borders (read by the soft-lock test of a neighbour), the candidate of
+// each round and a progress counter.  These are read and written only with
+// relaxed agent-scope atomics, which are coherent across the chip's L2
+// caches; a writer waits for its atomic stores to complete (vmcnt 0) before it
+// publishes the progress counter or the tag of a candidate, and a reader
+// issues its reads after it observed that counter or tag.  beta, z and the
+// DtD table are only ever touched by one workgroup during a launch and stay
+// in ordinary cached memory, so no cache write-back or invalidation is
+// needed between rounds.
+
+__device__ __forceinline__ unsigned long long ld_shared_u64(const unsigned long long *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_shared_u64(unsigned long long *p, unsigned long long v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int ld_shared_i32(const int *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_shared_i32(int *p, int v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+// Wait until every vector memory operation this wave issued has completed.
+__device__ __forceinline__ void wait_vm() {
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt/lgkmcnt untouched
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+// Shared best-move scores, accessed atomically.
+__device__ __forceinline__ float score_ld(const float *p) {
+  return __uint_as_float(__hip_atomic_load(reinterpret_cast<const unsigned *>(p), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ double score_ld(const double *p) {
+  return __longlong_as_double((long long)ld_shared_u64(reinterpret_cast<const unsigned long long *>(p)));
+}
+__device__ __forceinline__ void score_st(float *p, float v) {
+  __hip_atomic_store(reinterpret_cast<unsigned *>(p), __float_as_uint(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void score_st(double *p, double v) {
+  st_shared_u64(reinterpret_cast<unsigned long long *>(p), (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ uint32_t meta_pack(int argk, int nzc) { return (uint32_t)argk | ((uint32_t)nzc << 16); }
+__device__ __forceinline__ int meta_argk(uint32_t m) { return (int)(m & 0xffffu); }
+__device__ __forceinline__ int meta_nzc(uint32_t m) { return (int)(m >> 16); }
+
+// A candidate is two 64-bit words: the delta (word 1) and a tag word (word 0)
+// holding the round (22 bits), the atom (10 bits) and the position (32 bits;
+// all ones for "no accepted candidate").  Word 1 is stored and completed
+// before word 0.
+constexpr unsigned kNoPos = 0xffffffffu;
+constexpr int kRoundBits = 22;
+__device__ __forceinline__ unsigned long long cand_tag(int r, int k0, unsigned pos) {
+  return ((unsigned long long)(r & ((1 << kRoundBits) - 1)) << 42) | ((unsigned long long)(k0 & 0x3ff) << 32) |
+         (unsigned long long)pos;
+}
+__device__ __forceinline__ int tag_round(unsigned long long t) { return (int)(t >> 42); }
+__device__ __forceinline__ int tag_k0(unsigned long long t) { return (int)((t >> 32) & 0x3ff); }
+__device__ __forceinline__ unsigned tag_pos(unsigned long long t) { return (unsigned)(t & 0xffffffffull); }
+
+template <class R> __device__ __forceinline__ unsigned long long delta_bits(R d);
+template <> __device__ __forceinline__ unsigned long long delta_bits<float>(float d) { return __float_as_uint(d); }
+template <> __device__ __forceinline__ unsigned long long delta_bits<double>(double d) {
+  return (unsigned long long)__double_as_longlong(d);
+}
+template <class R> __device__ __forceinline__ R bits_delta(unsigned long long v);
+template <> __device__ __forceinline__ float bits_delta<float>(unsigned long long v) { return __uint_as_float((unsigned)v); }
+template <> __device__ __forceinline__ double bits_delta<double>(unsigned long long v) {
+  return __longlong_as_double((long long)v);
+}
+
+// Progress counters of the workers in `nbr` must reach `target`.  Returns
+// false after `timeout_ticks` of the 100 MHz clock.
+__device__ __forceinline__ bool wait_progress(const int *prog, const int *nbr, int nn, int self, int target,
+                                              long long timeout_ticks, int *sh_flag) {
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+    for (int q = 0; q < nn && ok; ++q) {
+      const int n = nbr[q];
+      if (n == self) continue;
+      while (ld_shared_i32(prog + n) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((long long)(__builtin_amdgcn_s_memrealtime() - t0) > timeout_ticks) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    *sh_flag = ok;
+  }
+  __syncthreads();
+  return *sh_flag != 0;
+}
+
+// ------------------------------------------------------------ block reductions
+
+// Largest (score, -pos): larger score wins, equal scores go to the lower pos.
+template <class R, int NT>
+__device__ __forceinline__ void block_argmax(R &s, int &pos, R *sh_s, int *sh_p) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    R os = __shfl_xor(s, off, 64);
+    int op = __shfl_xor(pos, off, 64);
+    if (os > s || (os == s && op < pos)) {
+      s = os;
+      pos = op;
+    }
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh_s[wave] = s;
+    sh_p[wave] = pos;
+  }
+  __syncthreads();
+  s = sh_s[0];
+  pos = sh_p[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) {
+    R os = sh_s[q];
+    int op = sh_p[q];
+    if (os > s || (os == s && op < pos)) {
+      s = os;
+      pos = op;
+    }
+  }
+  __syncthreads();
+}
+
+template <int NT>
+__device__ __forceinline__ int block_or(int v, int *sh) {
+  v = __any(v) ? 1 : 0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) r |= sh[q];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------- the round kernel
+//
+// One workgroup is one worker of Alg. 3 (DiCoDiLe-Z).  Worker w of an instance
+// owns S_w, a block of a W1 x W2 balanced split of the valid domain, cut into
+// sub-domains of tile1 x tile2 positions.  Round r visits sub-domain
+// (r mod mmax) and runs two phases:
+//   A  select the best move of the sub-domain from M (Alg. 1's local greedy
+//      choice), test it against the scores of the other workers' positions
+//      in its neighbourhood V(w0) (eq. soft_lock, lower worker index wins a
+//      tie) and publish the candidate (accepted or "none"), tagged with r;
+//   B  every worker applies, to the part of beta, z and M it owns, the
+//      accepted candidates of itself and of its grid neighbours whose
+//      neighbourhood meets S_w (eq. beta_update), in increasing worker order,
+//      then publishes progress r + 1.
+// Phase A of round r reads the border of S_w's neighbours, which only they
+// write, in their phase B: it starts once each neighbour's progress is >= r.
+// A neighbour starts its phase B of round r only after it has read this
+// worker's round-r candidate, which is published after this worker's phase A
+// reads.  Worker sizes of at least L_i keep every interaction between grid
+// neighbours.
+//
+// Stopping: a sweep is mmax rounds.  A sweep in which no worker found a move
+// scoring >= tol leaves the iterate unchanged, so every worker then exits.
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ insts,
+                                                   const int *__restrict__ wg_inst,
+                                                   long long timeout_ticks) {
+  constexpr int LBUF = 4096;  // partial maxima per LDS chunk
+  constexpr int NWAVE = NT / 64;
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  __shared__ R sh_ps[LBUF];
+  __shared__ uint16_t sh_pk[LBUF];
+  __shared__ R sh_inv_n[1024];
+  __shared__ R sh_rs[NWAVE];
+  __shared__ int sh_ri[NWAVE];
+  __shared__ int sh_exit;
+  __shared__ int sh_wait;
+  __shared__ int sh_cok;
+  __shared__ R sh_znew;
+  __shared__ unsigned long long sh_tag[9];
+  __shared__ R sh_delta[9];
+  __shared__ int sh_nbr[9];
+
+  const int ii = wg_inst[blockIdx.x];
+  const Inst<R> I = insts[ii];
+  const int tid = threadIdx.x;
+  const int w = blockIdx.x - I.wg_base;
+  const int nW = I.W1 * I.W2;
+  const int wi = w / I.W2, wj = w - wi * I.W2;
+  const int K = I.K, H = I.H, W = I.W;
+  const int a1 = part_start(wi, H, I.W1), b1 = part_start(wi + 1, H, I.W1);
+  const int a2 = part_start(wj, W, I.W2), b2 = part_start(wj + 1, W, I.W2);
+  const int nb1 = (b1 - a1 + I.tile1 - 1) / I.tile1, nb2 = (b2 - a2 + I.tile2 - 1) / I.tile2;
+  const int Mw = nb1 * nb2;
+  const int KS = I.KS;
+  const int G = KS / VE;  // vectors per position
+
+  for (int k = tid; k < KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
+  if (tid == 0) {
+    int nn = 0;
+    for (int di = -1; di <= 1; ++di)
+      for (int dj = -1; dj <= 1; ++dj) {
+        const int ni = wi + di, nj = wj + dj;
+        if (ni >= 0 && ni < I.W1 && nj >= 0 && nj < I.W2) sh_nbr[nn++] = ni * I.W2 + nj;
+      }
+    for (int q = nn; q < 9; ++q) sh_nbr[q] = -1;
+  }
+  __syncthreads();
+  int nbr[9];
+  int nn = 0;
+#pragma unroll
+  for (int q = 0; q < 9; ++q) {
+    nbr[q] = sh_nbr[q];
+    nn += nbr[q] >= 0;
+  }
+  // per-thread stepping of the flattened (position, vector) index by NT
+  const int spl = NT / G, sq = NT - (NT / G) * G;
+  const int pl0 = tid / G, q0 = tid - (tid / G) * G;
+
+  unsigned long long my_upd = 0, my_cand = 0, my_lock = 0, my_visit = 0, my_chk = 0, my_patch = 0;
+  unsigned long long tk_wait = 0, tk_sel = 0, tk_col = 0, tk_app = 0, tk_mark = 0;
+  int my_active = 0;
+  const unsigned long long t_launch = __builtin_amdgcn_s_memrealtime();
+  int r = 0;
+  int exit_status = 0;
+  for (;; ++r) {
+    // ---- exit conditions
+    if (tid == 0) {
+      int f = ld_shared_i32(&I.ctl->converged) | ld_shared_i32(&I.ctl->stop);
+      if (!f && I.max_rounds > 0 && r >= I.max_rounds) {
+        st_shared_i32(&I.ctl->stop, 1);
+        atomicCAS(&I.ctl->status, 0, 1);
+        f = 1;
+      }
+      if (!f && (long long)(__builtin_amdgcn_s_memrealtime() - t_launch) > I.budget_ticks) {
+        st_shared_i32(&I.ctl->stop, 1);
+        atomicCAS(&I.ctl->status, 0, 4);
+        f = 1;
+      }
+      sh_exit = f;
+      sh_cok = 1;
+    }
+    __syncthreads();
+    if (sh_exit) break;
+    if (tid == 0) tk_mark = __builtin_amdgcn_s_memrealtime();
+    if (!wait_progress(I.prog, nbr, nn, w, r, timeout_ticks, &sh_wait)) {
+      exit_status = 3;
+      break;
+    }
+    if (tid == 0) {
+      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+      tk_wait += t - tk_mark;
+      tk_mark = t;
+    }
+
+    // ---- phase A: locally greedy candidate of sub-domain m (Alg. 3, selection)
+    const int m = r % I.mmax;
+    R bs = R(-1);
+    int bp = 0x7fffffff;
+    if (m < Mw) {
+      ++my_visit;
+      const int bi = m / nb2, bj = m - (m / nb2) * nb2;
+      const int s1 = a1 + bi * I.tile1, e1 = min(s1 + I.tile1, b1);
+      const int s2 = a2 + bj * I.tile2, e2 = min(s2 + I.tile2, b2);
+      const int bw = e2 - s2, np = (e1 - s1) * bw;
+      for (int t = tid; t < np; t += NT) {
+        const int hh = s1 + t / bw, ww = s2 + t % bw;
+        const int pos = hh * W + ww;
+        const R sc = score_ld(I.score + pos);
+        if (sc > bs || (sc == bs && pos < bp)) {
+          bs = sc;
+          bp = pos;
+        }
+      }
+    }
+    block_argmax<R, NT>(bs, bp, sh_rs, sh_ri);
+    const bool has = bs >= I.tol && bs > R(0);
+    int h0 = 0, w0 = 0, k0 = -1;
+    if (has) {
+      h0 = bp / W;
+      w0 = bp - h0 * W;
+      my_active = 1;
+    }
+    int locked = 0;
+    if (has && I.soft_lock &&
+        (h0 - I.L1 + 1 < a1 || h0 + I.L1 > b1 || w0 - I.L2 + 1 < a2 || w0 + I.L2 > b2)) {
+      // soft-lock test over V(w0), inside the valid domain, outside S_w
+      const int v1 = max(h0 - I.L1 + 1, 0), u1 = min(h0 + I.L1, H);
+      const int v2 = max(w0 - I.L2 + 1, 0), u2 = min(w0 + I.L2, W);
+      const int vw = u2 - v2, nv = (u1 - v1) * vw;
+      my_chk += nv;
+      int lk = 0;
+      for (int t = tid; t < nv; t += NT) {
+        const int hh = v1 + t / vw, ww = v2 + t % vw;
+        if (hh >= a1 && hh < b1 && ww >= a2 && ww < b2) continue;
+        const R sc = score_ld(I.score + hh * W + ww);
+        if (sc > bs) {
+          lk = 1;
+        } else if (sc == bs) {
+          const int owner = part_owner(hh, H, I.W1) * I.W2 + part_owner(ww, W, I.W2);
+          if (owner < w) lk = 1;
+        }
+      }
+      locked = block_or<NT>(lk, sh_ri);
+    }
+    // the halo reads above must be complete before the candidate is visible
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) {
+      unsigned long long tag = cand_tag(r, 0, kNoPos);
+      unsigned long long dbits = 0;
+      if (has) {
+        ++my_cand;
+        if (locked) {
+          ++my_lock;
+        } else {
+          k0 = meta_argk(I.meta[bp]);
+          const long long i0 = (long long)bp * I.KS + k0;
+          const R zc = I.z[i0];
+          const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+          dbits = delta_bits<R>(zn - zc);
+          sh_znew = zn;
+          tag = cand_tag(r, k0, (unsigned)bp);
+          ++my_upd;
+          if (I.div_guard > R(0) && (zn > I.div_guard || -zn > I.div_guard)) {
+            st_shared_i32(&I.ctl->stop, 1);
+            atomicCAS(&I.ctl->status, 0, 2);
+          }
+        }
+      }
+      st_shared_u64(I.cand + 2 * w + 1, dbits);
+      wait_vm();
+      st_shared_u64(I.cand + 2 * w, tag);
+      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+      tk_sel += t - tk_mark;
+      tk_mark = t;
+    }
+
+    // ---- collect this round's candidates of the 3x3 neighbourhood
+    if (tid < nn) {
+      const int n = nbr[tid];
+      unsigned long long t = 0;
+      int ok = 1;
+      const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      for (;;) {
+        t = ld_shared_u64(I.cand + 2 * n);
+        if (tag_round(t) == (r & ((1 << kRoundBits) - 1))) break;
+        if (ld_shared_i32(I.prog + n) == 0x7fffffff) {  // neighbour has left
+          t = cand_tag(r, 0, kNoPos);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        if ((long long)(__builtin_amdgcn_s_memrealtime() - t0) > timeout_ticks) {
+          ok = 0;
+          t = cand_tag(r, 0, kNoPos);
+          break;
+        }
+      }
+      sh_tag[tid] = t;
+      sh_delta[tid] = tag_pos(t) != kNoPos ? bits_delta<R>(ld_shared_u64(I.cand + 2 * n + 1)) : R(0);
+      if (!ok) sh_cok = 0;
+    }
+    __syncthreads();
+    if (!sh_cok) {
+      exit_status = 3;
+      break;
+    }
+    if (tid == 0) {
+      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+      tk_col += t - tk_mark;
+      tk_mark = t;
+    }
+
+    // ---- phase B: apply accepted updates that touch S_w (eq. beta_update)
+    for (int q = 0; q < nn; ++q) {
+      const unsigned long long tg = sh_tag[q];
+      const unsigned cpos = tag_pos(tg);
+      if (cpos == kNoPos) continue;
+      const int ck = tag_k0(tg);
+      const int ch = (int)(cpos / (unsigned)W), cw0 = (int)(cpos - (unsigned)ch * (unsigned)W);
+      const R delta = sh_delta[q];
+      const int r1 = max(ch - I.L1 + 1, a1), r2 = min(ch + I.L1, b1);
+      const int c1 = max(cw0 - I.L2 + 1, a2), c2 = min(cw0 + I.L2, b2);
+      if (r1 >= r2 || c1 >= c2) continue;
+      if (nbr[q] == w && tid == 0) {
+        const long long i0 = (long long)cpos * KS + ck;
+        const R zold = I.z[i0];
+        const R znew = sh_znew;
+        I.z[i0] = znew;
+        const uint32_t mt = I.meta[cpos];
+        I.meta[cpos] = meta_pack(meta_argk(mt), meta_nzc(mt) + (znew != R(0)) - (zold != R(0)));
+        wait_vm();
+      }
+      __syncthreads();
+      const int nc = c2 - c1;
+      my_patch += (unsigned long long)(r2 - r1) * nc;
+      const int cw = min(nc, LBUF / G);
+      const int rc = max(1, LBUF / (cw * G));
+      const int cg = ck / VE, ce = ck - cg * VE;
+      for (int rr0 = r1; rr0 < r2; rr0 += rc) {
+        const int rr1 = min(rr0 + rc, r2);
+        for (int cc0 = c1; cc0 < c2; cc0 += cw) {
+          const int ccw = min(cw, c2 - cc0);
+          const int ng = ccw * G;
+          for (int rr = rr0; rr < rr1; ++rr) {
+            V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
+            const V *__restrict__ arow = reinterpret_cast<const V *>(
+                I.A + (((long long)ck * I.U1 + (rr - ch + I.L1 - 1)) * I.U2 + (cc0 - cw0 + I.L2 - 1)) * KS);
+            const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
+            const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
+            const int gself = (rr == ch && cw0 >= cc0 && cw0 < cc0 + ccw) ? (cw0 - cc0) * G + cg : -1;
+            R *prow = sh_ps + (rr - rr0) * ng;
+            uint16_t *krow = sh_pk + (rr - rr0) * ng;
+            int pl = pl0, qq = q0;
+#pragma unroll 4
+            for (int j = tid; j < ng; j += NT) {
+              V b = brow[j];
+              const V av = arow[j];
+              const uint32_t mt = mrow[pl];
+              const V bold = b;
+              b = Vec<R>::fma_neg(b, av, delta);
+              if (j == gself) Vec<R>::set(b, ce, Vec<R>::get(bold, ce));  // beta at (k0, w0) is unchanged
+              brow[j] = b;
+              const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
+              R best = R(-1);
+              int bk = 0;
+#pragma unroll
+              for (int e = 0; e < VE; ++e) {
+                const int k = qq * VE + e;
+                const R zn = st_target(Vec<R>::get(b, e), I.lambda, sh_inv_n[k], I.positive);
+                const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
+                if (sc > best) {
+                  best = sc;
+                  bk = k;
+                }
+              }
+              prow[j] = best;
+              krow[j] = (uint16_t)bk;
+              qq += sq;
+              pl += spl;
+              if (qq >= G) {
+                qq -= G;
+                pl += 1;
+              }
+            }
+          }
+          __syncthreads();
+          const int npos = (rr1 - rr0) * ccw;
+          for (int t = tid; t < npos; t += NT) {
+            const int rr = rr0 + t / ccw, pl = t % ccw;
+            const int pos = rr * W + cc0 + pl;
+            const R *pp = sh_ps + t * G;
+            const uint16_t *pk = sh_pk + t * G;
+            R best = pp[0];
+            int bk = pk[0];
+            for (int g = 1; g < G; ++g)
+              if (pp[g] > best) {
+                best = pp[g];
+                bk = pk[g];
+              }
+            score_st(I.score + pos, best);
+            I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
+          }
+          __syncthreads();
+        }
+      }
+    }
+    // score stores complete before the progress counter moves
+    wait_vm();
+    __syncthreads();
+    if (tid == 0) {
+      st_shared_i32(I.prog + w, r + 1);
+      tk_app += __builtin_amdgcn_s_memrealtime() - tk_mark;
+    }
+
+    // ---- sweep bookkeeping and the global stopping consensus
+    if ((r + 1) % I.mmax == 0) {
+      if (tid == 0) {
+        const int s = r / I.mmax;
+        const int slot = s % kRing;
+        int *done = I.ring, *active = I.ring + kRing;
+        // the activity count lands before the completion count that reports it
+        if (my_active) __hip_atomic_fetch_add(&active[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        wait_vm();
+        const int old = __hip_atomic_fetch_add(&done[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == nW - 1) {
+          const int act = ld_shared_i32(&active[slot]);
+          st_shared_i32(&active[slot], 0);
+          st_shared_i32(&done[slot], 0);
+          atomicMax(&I.ctl->sweeps_done, s + 1);
+          if (act == 0) st_shared_i32(&I.ctl->converged, 1);
+        }
+      }
+      my_active = 0;
+    }
+  }
+  // ---- leave: neighbours must never wait on a finished worker
+  wait_vm();
+  __syncthreads();
+  if (tid == 0) {
+    if (exit_status) {
+      st_shared_i32(&I.ctl->stop, 1);
+      atomicCAS(&I.ctl->status, 0, exit_status);
+    }
+    atomicAdd(&I.ctl->n_updates, my_upd);
+    atomicAdd(&I.ctl->n_candidates, my_cand);
+    atomicAdd(&I.ctl->n_softlocked, my_lock);
+    atomicAdd(&I.ctl->n_visits, my_visit);
+    atomicAdd(&I.ctl->n_checked, my_chk);
+    atomicAdd(&I.ctl->n_patched, my_patch);
+    atomicAdd(&I.ctl->tk_wait, tk_wait);
+    atomicAdd(&I.ctl->tk_select, tk_sel);
+    atomicAdd(&I.ctl->tk_collect, tk_col);
+    atomicAdd(&I.ctl->tk_apply, tk_app);
+    atomicMax(&I.ctl->max_round, r);
+    st_shared_i32(I.prog + w, 0x7fffffff);
+  }
+}
+
+}  // namespace dcdl

@@ -1,0 +1,385 @@
+// dcdl_kernels.h -- gfx950 kernels around the round kernel: DtD, correlation
+// (beta initialisation, drift correction, FP64 check, lambda_max), residual,
+// layout changes, reductions and the dictionary statistics of Sec. 4.2.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dcdl_device.h"
+
+namespace dcdl {
+
+struct Geom {
+  int P, K, L1, L2, U1, U2;
+  int T1, T2, H, W;
+  int KS;  // atom stride of position-major arrays (>= K)
+};
+
+// Non-negative doubles order like their bit patterns as unsigned integers.
+__device__ __forceinline__ void atomic_max_nonneg(double *addr, double v) {
+  atomicMax(reinterpret_cast<unsigned long long *>(addr), (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void atomic_add_f64(double *addr, double v) { unsafeAtomicAdd(addr, v); }
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < NT / 64; ++q) s += sh[q];
+  __syncthreads();
+  return s;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_max(double v, double *sh) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = sh[0];
+#pragma unroll
+  for (int q = 1; q < NT / 64; ++q) s = fmax(s, sh[q]);
+  __syncthreads();
+  return s;
+}
+
+// --------------------------------------------------------------------- DtD
+// One workgroup per (k0, k): dtd[k0][k][u] = sum_p sum_t D[k0,p,t] D[k,p,t+tau],
+// tau = u - (L - 1), accumulated in FP64.  Also writes the apply table
+// A[k0][U1-1-u1][U2-1-u2][k] (the same value, indexed by the offset of the
+// patched position from the update; atom stride KS, padding left as set by the
+// caller) and 1/||D_k||^2.
+template <class R>
+__global__ __launch_bounds__(256) void dtd_kernel(Geom g, const R *__restrict__ D, R *__restrict__ dtd,
+                                                  R *__restrict__ A, R *__restrict__ inv_n) {
+  extern __shared__ unsigned char smem_raw[];
+  R *d0 = reinterpret_cast<R *>(smem_raw);
+  const int PL = g.P * g.L1 * g.L2;
+  R *d1 = d0 + PL;
+  const int k0 = blockIdx.x / g.K, k = blockIdx.x - k0 * g.K;
+  for (int i = threadIdx.x; i < PL; i += blockDim.x) {
+    d0[i] = D[(long long)k0 * PL + i];
+    d1[i] = D[(long long)k * PL + i];
+  }
+  __syncthreads();
+  const int nU = g.U1 * g.U2;
+  for (int u = threadIdx.x; u < nU; u += blockDim.x) {
+    const int u1 = u / g.U2, u2 = u - (u / g.U2) * g.U2;
+    const int tau1 = u1 - (g.L1 - 1), tau2 = u2 - (g.L2 - 1);
+    const int t1lo = max(0, -tau1), t1hi = min(g.L1, g.L1 - tau1);
+    const int t2lo = max(0, -tau2), t2hi = min(g.L2, g.L2 - tau2);
+    double s = 0.0;
+    for (int p = 0; p < g.P; ++p)
+      for (int t1 = t1lo; t1 < t1hi; ++t1) {
+        const R *a = d0 + (p * g.L1 + t1) * g.L2;
+        const R *b = d1 + (p * g.L1 + t1 + tau1) * g.L2 + tau2;
+        for (int t2 = t2lo; t2 < t2hi; ++t2) s += (double)a[t2] * (double)b[t2];
+      }
+    dtd[((long long)blockIdx.x) * nU + u] = (R)s;
+    A[(((long long)k0 * g.U1 + (g.U1 - 1 - u1)) * g.U2 + (g.U2 - 1 - u2)) * g.KS + k] = (R)s;
+    if (k == k0 && tau1 == 0 && tau2 == 0) inv_n[k] = (R)(1.0 / s);
+  }
+}
+
+// ------------------------------------------------------------- correlation
+// G[pos][k] = sum_p sum_t D[k,p,t] X[p, pos + t] on the valid domain, computed
+// directly: one thread per output position, KC atoms at a time, the slice
+// D[k-chunk, p, t1, :] staged in LDS.  Tile: 8 rows x 32 columns of positions.
+enum CorrMode { CORR_BETA = 0, CORR_KKT = 1, CORR_ABSMAX = 2 };
+
+struct CorrOut {
+  void *beta;          // CORR_BETA: (H, W, KS) in the output type, padding written as 0
+  const void *zpm;     // z (H, W, KS) in the working type: + n_k z (BETA) or the KKT test
+  const double *nrm;   // n_k in FP64 (CORR_BETA with zpm)
+  double lambda;       // CORR_KKT
+  int positive;        // CORR_KKT / CORR_ABSMAX
+  double *result;      // CORR_KKT: max violation; CORR_ABSMAX: max |G| (one-sided if positive)
+};
+
+template <class Rin, class Racc, class Rz, int MODE, int KC>
+__global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict__ X, const Rin *__restrict__ D,
+                                                   CorrOut o) {
+  constexpr int TH = 8, TW = 32;
+  extern __shared__ unsigned char smem_raw[];
+  Racc *ds = reinterpret_cast<Racc *>(smem_raw);  // [L2][KC]
+  __shared__ double sh_red[4];
+  const int tx = threadIdx.x % TW, ty = threadIdx.x / TW;
+  const int h = blockIdx.y * TH + ty, w = blockIdx.x * TW + tx;
+  const bool valid = h < g.H && w < g.W;
+  const long long plane = (long long)g.T1 * g.T2;
+  const long long pos = (long long)h * g.W + w;
+  double red = 0.0;
+  for (int kb = 0; kb < g.K; kb += KC) {
+    const int kc = min(KC, g.K - kb);
+    Racc acc[KC];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) acc[q] = Racc(0);
+    for (int p = 0; p < g.P; ++p)
+      for (int t1 = 0; t1 < g.L1; ++t1) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < g.L2 * KC; i += blockDim.x) {
+          const int t2 = i / KC, q = i - (i / KC) * KC;
+          ds[i] = q < kc ? (Racc)D[(((long long)(kb + q) * g.P + p) * g.L1 + t1) * g.L2 + t2] : Racc(0);
+        }
+        __syncthreads();
+        if (valid) {
+          const Rin *xr = X + p * plane + (long long)(h + t1) * g.T2 + w;
+          for (int t2 = 0; t2 < g.L2; ++t2) {
+            const Racc x = (Racc)xr[t2];
+            const Racc *dr = ds + t2 * KC;
+#pragma unroll
+            for (int q = 0; q < KC; ++q) acc[q] += dr[q] * x;
+          }
+        }
+      }
+    if (valid) {
+#pragma unroll
+      for (int q = 0; q < KC; ++q) {
+        if (q >= kc) break;
+        const int k = kb + q;
+        if (MODE == CORR_BETA) {
+          double v = (double)acc[q];
+          if (o.zpm) v += o.nrm[k] * (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+          reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = (Rz)v;
+        } else if (MODE == CORR_KKT) {
+          const double gv = (double)acc[q];
+          const double z = (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+          double v;
+          if (z == 0.0)
+            v = o.positive ? fmax(gv - o.lambda, 0.0) : fmax(fabs(gv) - o.lambda, 0.0);
+          else
+            v = fabs(gv - (z > 0.0 ? o.lambda : -o.lambda));
+          red = fmax(red, v);
+        } else {
+          const double gv = (double)acc[q];
+          red = fmax(red, o.positive ? gv : fabs(gv));
+        }
+      }
+    }
+  }
+  if (MODE == CORR_BETA && valid)
+    for (int k = g.K; k < g.KS; ++k) reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = Rz(0);
+  if (MODE != CORR_BETA) {
+    red = block_max<256>(red, sh_red);
+    if (threadIdx.x == 0) atomic_max_nonneg(o.result, fmax(red, 0.0));
+  }
+}
+
+// ------------------------------------------------------- best-move cache
+// score[pos] = max_k score of the move at (k, pos); meta[pos] = (its atom,
+// number of non-zero atoms), from beta and z (atom stride KS).
+template <class R>
+__global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R *__restrict__ beta,
+                                                  const R *__restrict__ z, const R *__restrict__ inv_n, R lambda,
+                                                  R tol, int positive, int certify, R *__restrict__ score,
+                                                  uint32_t *__restrict__ meta) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= HW) return;
+  R best = R(-1);
+  int bk = 0, nz = 0;
+  for (int k = 0; k < K; ++k) {
+    const R zk = z[(long long)pos * KS + k];
+    nz += zk != R(0);
+    const R zn = st_target(beta[(long long)pos * KS + k], lambda, inv_n[k], positive);
+    const R sc = move_score(zk, zn, tol, certify);
+    if (sc > best) {
+      best = sc;
+      bk = k;
+    }
+  }
+  score[pos] = best;
+  meta[pos] = (uint32_t)bk | ((uint32_t)nz << 16);
+}
+
+// ---------------------------------------------------------------- layouts
+// user (K, H*W) <-> position-major (H*W, KS) with zero padding, and a type change.
+template <class Rs, class Rd>
+__global__ __launch_bounds__(256) void to_position_major(int HW, int K, int KS, const Rs *__restrict__ src,
+                                                         Rd *__restrict__ dst) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= HW) return;
+  for (int k = 0; k < KS; ++k) dst[(long long)pos * KS + k] = k < K ? (Rd)src[(long long)k * HW + pos] : Rd(0);
+}
+
+template <class Rs, class Rd>
+__global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, const Rs *__restrict__ src,
+                                                     Rd *__restrict__ dst) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= HW) return;
+  for (int k = 0; k < K; ++k) dst[(long long)k * HW + pos] = (Rd)src[(long long)pos * KS + k];
+}
+
+template <class Rs, class Rd>
+__global__ __launch_bounds__(256) void convert_kernel(long long n, const Rs *__restrict__ src, Rd *__restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = (Rd)src[i];
+}
+
+// --------------------------------------------------------- sparse residual
+struct NzEntry {
+  int pos;
+  int k;
+  double z;
+};
+
+// Counts (list == nullptr) or lists the non-zeros of a position-major z of
+// atom stride KS, and accumulates sum |z| in FP64.
+template <class R>
+__global__ __launch_bounds__(256) void collect_nonzeros(long long n, int KS, const R *__restrict__ z,
+                                                        unsigned long long *count, NzEntry *list,
+                                                        unsigned long long cap, double *l1) {
+  __shared__ double sh[4];
+  double a = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const R v = z[i];
+    if (v != R(0)) {
+      a += fabs((double)v);
+      const unsigned long long slot = atomicAdd(count, 1ull);
+      if (list && slot < cap) {
+        NzEntry e;
+        e.pos = (int)(i / KS);
+        e.k = (int)(i - (i / KS) * KS);
+        e.z = (double)v;
+        list[slot] = e;
+      }
+    }
+  }
+  if (l1) {
+    a = block_sum<256>(a, sh);
+    if (threadIdx.x == 0) atomic_add_f64(l1, a);
+  }
+}
+
+// res -= z * D_k shifted to pos, for every listed non-zero (eq. model).
+template <class Rd>
+__global__ __launch_bounds__(256) void scatter_atoms(Geom g, const NzEntry *__restrict__ list, long long nnz,
+                                                     const Rd *__restrict__ D, double *__restrict__ res) {
+  const int PL = g.P * g.L1 * g.L2;
+  const long long plane = (long long)g.T1 * g.T2;
+  for (long long e = blockIdx.x; e < nnz; e += gridDim.x) {
+    const NzEntry nz = list[e];
+    const int h = nz.pos / g.W, w = nz.pos - (nz.pos / g.W) * g.W;
+    const Rd *dk = D + (long long)nz.k * PL;
+    for (int i = threadIdx.x; i < PL; i += blockDim.x) {
+      const int p = i / (g.L1 * g.L2), r = i - p * (g.L1 * g.L2);
+      const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
+      atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -nz.z * (double)dk[i]);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void sum_squares(long long n, const double *__restrict__ x, double *out) {
+  __shared__ double sh[4];
+  double a = 0.0;
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    a += x[i] * x[i];
+  a = block_sum<256>(a, sh);
+  if (threadIdx.x == 0) atomic_add_f64(out, a);
+}
+
+// ------------------------------------------------------- dictionary stats
+// psi[k][p][t] += sum over the non-zeros of atom k in [beg, end) of z X_p[pos + t].
+// One workgroup per chunk; every chunk holds non-zeros of a single atom.
+struct Chunk {
+  int k;
+  int beg;
+  int end;
+  int pad;
+};
+
+template <class Rin>
+__global__ __launch_bounds__(256) void psi_kernel(Geom g, const Chunk *__restrict__ chunks, const NzEntry *__restrict__ list,
+                                                  const Rin *__restrict__ X, double *__restrict__ psi) {
+  __shared__ NzEntry sh_nz[128];
+  const Chunk c = chunks[blockIdx.x];
+  const int PL = g.P * g.L1 * g.L2, LL = g.L1 * g.L2;
+  const long long plane = (long long)g.T1 * g.T2;
+  const int n = c.end - c.beg;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sh_nz[i] = list[c.beg + i];
+  __syncthreads();
+  for (int e = threadIdx.x; e < PL; e += blockDim.x) {
+    const int p = e / LL, r = e - p * LL;
+    const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
+    const Rin *xp = X + p * plane + (long long)t1 * g.T2 + t2;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) {
+      const int pos = sh_nz[j].pos;
+      const int h = pos / g.W, w = pos - (pos / g.W) * g.W;
+      acc += sh_nz[j].z * (double)xp[(long long)h * g.T2 + w];
+    }
+    atomic_add_f64(psi + (long long)c.k * PL + e, acc);
+  }
+}
+
+// phi[k][k'][tau + L - 1] += z_k[w] z_k'[w + tau] for every listed non-zero
+// (k, w), scanning its window w + Phi in a position-major copy of z.
+template <class R>
+__global__ __launch_bounds__(256) void phi_kernel(Geom g, const NzEntry *__restrict__ list, long long nnz,
+                                                  const R *__restrict__ zpm, const int *__restrict__ nzc,
+                                                  double *__restrict__ phi) {
+  const int nU = g.U1 * g.U2;
+  for (long long e = blockIdx.x; e < nnz; e += gridDim.x) {
+    const NzEntry nz = list[e];
+    const int h = nz.pos / g.W, w = nz.pos - (nz.pos / g.W) * g.W;
+    for (int u = threadIdx.x; u < nU; u += blockDim.x) {
+      const int u1 = u / g.U2, u2 = u - (u / g.U2) * g.U2;
+      const int hh = h + u1 - (g.L1 - 1), ww = w + u2 - (g.L2 - 1);
+      if (hh < 0 || hh >= g.H || ww < 0 || ww >= g.W) continue;
+      const int pos2 = hh * g.W + ww;
+      if (nzc[pos2] == 0) continue;
+      const R *zr = zpm + (long long)pos2 * g.KS;
+      for (int k2 = 0; k2 < g.K; ++k2) {
+        const R v = zr[k2];
+        if (v != R(0)) atomic_add_f64(phi + ((long long)nz.k * g.K + k2) * nU + u, nz.z * (double)v);
+      }
+    }
+  }
+}
+
+// Non-zero atoms per position of a position-major z.
+template <class R>
+__global__ __launch_bounds__(256) void count_per_position(int HW, int K, int KS, const R *__restrict__ zpm,
+                                                          int *__restrict__ nzc) {
+  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pos >= HW) return;
+  int c = 0;
+  for (int k = 0; k < K; ++k) c += zpm[(long long)pos * KS + k] != R(0);
+  nzc[pos] = c;
+}
+
+// Per-atom counts of the non-zeros of an atom-major z (K, HW).
+template <class R>
+__global__ __launch_bounds__(256) void count_per_atom(int HW, int K, const R *__restrict__ z, unsigned int *__restrict__ cnt) {
+  const int k = blockIdx.y;
+  unsigned int c = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += gridDim.x * blockDim.x)
+    c += z[(long long)k * HW + i] != R(0);
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&cnt[k], c);
+}
+
+// Lists the non-zeros of an atom-major z grouped by atom: cursor[k] starts at
+// the atom's offset in the list.
+template <class R>
+__global__ __launch_bounds__(256) void list_per_atom(int HW, int K, const R *__restrict__ z,
+                                                     unsigned int *__restrict__ cursor, NzEntry *__restrict__ list) {
+  const int k = blockIdx.y;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += gridDim.x * blockDim.x) {
+    const R v = z[(long long)k * HW + i];
+    if (v != R(0)) {
+      const unsigned int slot = atomicAdd(&cursor[k], 1u);
+      NzEntry e;
+      e.pos = i;
+      e.k = k;
+      e.z = (double)v;
+      list[slot] = e;
+    }
+  }
+}
+
+}  // namespace dcdl

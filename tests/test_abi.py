@@ -1,0 +1,97 @@
+"""The C ABI without a GPU: the library builds, exports every declared entry
+point, its structs have the layout the header states, and argument checks that
+run before any device access return the documented codes."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dicodile.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_1901_09235_amd as dl
+    from paper_1901_09235_amd import build
+    if not os.path.exists(dl.library_path()):
+        build.build()
+    return dl.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\w[\w\s\*]*?\b(dicodile_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 8
+    out = subprocess.run(["nm", "-D", "--defined-only", lib._name], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\bT (dicodile_\w+)", out))
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert hasattr(lib, n)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Compile a plain C probe against the header and compare sizes/offsets
+    with the ctypes mirrors of the binding."""
+    import paper_1901_09235_amd as dl
+    src = tmp_path / "probe.c"
+    src.write_text("""
+#include <stdio.h>
+#include <stddef.h>
+#include "dicodile.h"
+int main(void) {
+  printf("%zu %zu %zu\\n", sizeof(dcdl_shape), sizeof(dcdl_csc_opts), sizeof(dcdl_csc_info));
+  printf("%zu %zu %zu %zu\\n", offsetof(dcdl_csc_opts, max_rounds), offsetof(dcdl_csc_opts, kkt_target),
+         offsetof(dcdl_csc_info, converged), offsetof(dcdl_csc_info, n_passes));
+  return 0;
+}
+""")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    lines = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    sizes = [int(v) for v in lines[0].split()]
+    offs = [int(v) for v in lines[1].split()]
+    assert sizes == [ctypes.sizeof(dl.Shape), ctypes.sizeof(dl.CscOpts), ctypes.sizeof(dl.CscInfo)]
+    assert offs == [dl.CscOpts.max_rounds.offset, dl.CscOpts.kkt_target.offset,
+                    dl.CscInfo.converged.offset, dl.CscInfo.n_passes.offset]
+
+
+def test_argument_checks_before_device_access(lib):
+    import paper_1901_09235_amd as dl
+    assert lib.dicodile_version().startswith(b"dicodile-mi355x")
+    # NULL shape
+    rc = lib.dicodile_dtd(None, 0, None, None, None)
+    assert rc == -1 and b"shape" in lib.dicodile_last_error()
+    s = dl.Shape()
+    s.ndim, s.P, s.K = 3, 1, 1
+    assert lib.dicodile_dtd(ctypes.byref(s), 0, None, None, None) == -1
+    s.ndim, s.T[0], s.L[0] = 1, 10, 20  # L > T
+    assert lib.dicodile_dtd(ctypes.byref(s), 0, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+    s.L[0] = 4
+    o = dl.make_opts(-1.0, 0.0, 0)
+    info = dl.CscInfo()
+    rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(o),
+                          ctypes.c_void_p(1), ctypes.byref(info), None)
+    assert rc == -1 and b"lambda" in lib.dicodile_last_error()
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    import paper_1901_09235_amd as dl
+    monkeypatch.setattr(dl, "_lib", None)
+    monkeypatch.setattr(dl, "_LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(dl.DicodileError):
+        dl.load()
+
+
+def test_oracle_builds_with_gcc():
+    import oracle
+    path = oracle.build(force=True)
+    assert os.path.exists(path)

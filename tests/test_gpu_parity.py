@@ -1,0 +1,212 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+The Lasso minimiser is unique for these random dictionaries, but the GPU's
+update order differs from the sequential oracle, so solves are compared by
+relative objective gap <= 1e-6 and strict KKT <= 1e-4 (in units of lambda),
+the two criteria of the target; operators (DtD, lambda_max, objective, KKT,
+dictionary statistics) are compared element by element.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09235_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_09235_amd as dl
+    dl.load()
+    return dl
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def host(t):
+    return t.detach().cpu().double().numpy()
+
+
+def _small_image(seed, size=(64, 72), K=4, L=(8, 8), P=1, rho=0.01):
+    return synth.make_problem("t", seed, P=P, T=size, K=K, L=L, rho=rho, amp="uniform", sigma=0.1)
+
+
+def _small_signal(seed, T=900, K=3, L=32, P=2, rho=0.01):
+    return synth.make_problem("t", seed, P=P, T=T, K=K, L=L, rho=rho, amp="uniform", sigma=0.1)
+
+
+# ----------------------------------------------------------------- operators
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("case", ["img", "sig", "rgb"])
+def test_dtd_matches_oracle(lib, dtype, case):
+    pb = {"img": _small_image(1), "sig": _small_signal(2), "rgb": _small_image(3, P=3, L=(5, 7))}[case]
+    C = host(lib.dicodile_dtd(dev(pb.D, dtype)))
+    ref = oracle.dtd(pb.D)
+    tol = 1e-12 if dtype == torch.float64 else 1e-6
+    np.testing.assert_allclose(C, ref, rtol=0, atol=tol * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_lambda_max_matches_oracle(lib, positive):
+    for pb in (_small_image(4), _small_signal(5), synth.signal_1d()):
+        lm = lib.dicodile_lambda_max(dev(pb.X, torch.float64), dev(pb.D, torch.float64), positive)
+        assert lm == pytest.approx(oracle.lambda_max(pb.X, pb.D, positive), rel=1e-13)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_objective_and_kkt_match_oracle(lib, dtype):
+    pb = _small_image(6, P=2)
+    rng = np.random.default_rng(0)
+    Z = pb.Z_true * (1 + 0.1 * rng.standard_normal(pb.Z_true.shape))
+    if dtype == torch.float32:
+        Z = Z.astype(np.float32).astype(np.float64)
+        X, D = pb.X.astype(np.float32).astype(np.float64), pb.D.astype(np.float32).astype(np.float64)
+    else:
+        X, D = pb.X, pb.D
+    lam = 0.1 * oracle.lambda_max(X, D)
+    obj, kkt = lib.dicodile_objective_kkt(dev(X, dtype), dev(D, dtype), dev(Z, dtype), lam)
+    assert obj == pytest.approx(oracle.objective(X, D, Z, lam), rel=1e-12)
+    assert kkt == pytest.approx(oracle.kkt(X, D, Z, lam), rel=1e-9)
+
+
+# ------------------------------------------------------------------- solver
+
+def _solve_and_compare(lib, pb, dtype, grid=None, tile=None, positive=False, threads=0,
+                       obj_tol=1e-6, kkt_tol=1e-4, tol_rel=None):
+    lam = pb.lambda_frac * oracle.lambda_max(pb.X, pb.D, positive)
+    if dtype == torch.float64:
+        tol = 1e-10 * lam if tol_rel is None else tol_rel * lam
+        X, D = pb.X, pb.D
+    else:
+        tol = 1e-5 * lam if tol_rel is None else tol_rel * lam
+        X = pb.X.astype(np.float32).astype(np.float64)
+        D = pb.D.astype(np.float32).astype(np.float64)
+    z, info = lib.dicodile_csc(dev(X, dtype), dev(D, dtype), lam, tol, positive=positive,
+                               grid=grid, tile=tile, threads=threads, max_rounds=2_000_000,
+                               timeout_s=60)
+    assert info["status"] == "OK", info
+    Zg = host(z)
+    Zo, oinfo = oracle.lgcd(X, D, lam, 1e-10 * lam, positive=positive)
+    fo = oracle.objective(X, D, Zo, lam)
+    fg = oracle.objective(X, D, Zg, lam)
+    assert (fg - fo) / abs(fo) <= obj_tol, (fg, fo, info)
+    assert oracle.kkt(X, D, Zg, lam, positive) <= kkt_tol
+    assert info["kkt"] == pytest.approx(oracle.kkt(X, D, Zg, lam, positive), rel=1e-6, abs=1e-12)
+    assert info["objective"] == pytest.approx(fg, rel=1e-10)
+    if positive:
+        assert (Zg >= 0).all()
+    return Zg, info
+
+
+@pytest.mark.parametrize("W", [1, 2, 4, 8, 16])
+def test_csc_signal_1d_fp64_every_grid(lib, W):
+    """The 1-D FP64 workload (T=5000, K=5, L=64) on 1..16 workers."""
+    pb = synth.signal_1d()
+    Zg, info = _solve_and_compare(lib, pb, torch.float64, grid=W, tol_rel=None)
+    assert info["grid"] == (1, W)
+    assert info["n_updates"] > 0
+
+
+@pytest.mark.parametrize("threads", [64, 256])
+def test_csc_small_image_fp32(lib, threads):
+    pb = _small_image(7)
+    _solve_and_compare(lib, pb, torch.float32, threads=threads)
+
+
+def test_csc_small_image_fp64_grid_and_ragged_tiles(lib):
+    pb = _small_image(8, size=(77, 61), K=3, L=(6, 5))
+    _, info = _solve_and_compare(lib, pb, torch.float64, grid=(3, 4), tile=(7, 9))
+    assert info["n_softlocked"] >= 0 and info["grid"] == (3, 4)
+
+
+def test_csc_multichannel_positive(lib):
+    pb = _small_image(9, P=3, L=(6, 6))
+    _solve_and_compare(lib, pb, torch.float32, positive=True)
+
+
+def test_csc_image_crop_k25_l16_fp32(lib):
+    """The image workload's atoms (K=25, 16x16) on a 112x112 crop."""
+    pb = synth.image_1024(seed=2000, size=112)
+    _solve_and_compare(lib, pb, torch.float32)
+
+
+# -------------------------------------------------------------- edge cases
+
+def test_lambda_above_lambda_max_gives_exact_zero(lib):
+    pb = _small_image(10)
+    lm = oracle.lambda_max(pb.X, pb.D)
+    z, info = lib.dicodile_csc(dev(pb.X, torch.float64), dev(pb.D, torch.float64), lm * 1.0001, 0.0,
+                               max_rounds=100000, timeout_s=30)
+    assert info["status"] == "OK" and info["n_updates"] == 0
+    assert not host(z).any()
+
+
+def test_single_position_domain(lib):
+    """T = L: one position, a dense K-column Lasso."""
+    rng = np.random.default_rng(11)
+    D = rng.standard_normal((6, 2, 3, 3))
+    D /= np.sqrt((D ** 2).sum(axis=(1, 2, 3)))[:, None, None, None]
+    X = rng.standard_normal((2, 3, 3))
+    lam = 0.2 * oracle.lambda_max(X, D)
+    z, info = lib.dicodile_csc(dev(X, torch.float64), dev(D, torch.float64), lam, 1e-12,
+                               max_rounds=100000, timeout_s=30)
+    Zo, _ = oracle.lgcd(X, D, lam, 1e-13)
+    assert oracle.objective(X, D, host(z), lam) == pytest.approx(oracle.objective(X, D, Zo, lam), rel=1e-12)
+
+
+def test_warm_start_at_solution_converges_at_once(lib):
+    pb = _small_signal(12)
+    lam = 0.1 * oracle.lambda_max(pb.X, pb.D)
+    Zo, _ = oracle.lgcd(pb.X, pb.D, lam, 1e-12 * lam)
+    z0 = dev(Zo, torch.float64)
+    z, info = lib.dicodile_csc(dev(pb.X, torch.float64), dev(pb.D, torch.float64), lam, 1e-9 * lam,
+                               z_out=z0, warm_start=True, max_rounds=100000, timeout_s=30)
+    assert info["status"] == "OK"
+    assert info["n_updates"] <= 5
+
+
+def test_round_cap_reports_not_converged(lib):
+    pb = _small_image(13)
+    lam = 0.1 * oracle.lambda_max(pb.X, pb.D)
+    z, info = lib.dicodile_csc(dev(pb.X, torch.float64), dev(pb.D, torch.float64), lam, 1e-10 * lam,
+                               max_rounds=3, timeout_s=30)
+    assert info["status"] == "NOT_CONVERGED"
+    f0 = oracle.objective(pb.X, pb.D, np.zeros_like(pb.Z_true), lam)
+    assert oracle.objective(pb.X, pb.D, host(z), lam) < f0
+
+
+def test_invalid_arguments_raise(lib):
+    pb = _small_image(14)
+    X, D = dev(pb.X, torch.float64), dev(pb.D, torch.float64)
+    with pytest.raises(lib.DicodileError):
+        lib.dicodile_csc(X, D, -1.0, 0.0)
+    with pytest.raises(lib.DicodileError):
+        lib.dicodile_csc(X, D, 1.0, 0.0, grid=(60, 1))  # workers shorter than the atom
+    with pytest.raises(lib.DicodileError):
+        lib.dicodile_csc(X, D[:, :, :4, :4].contiguous(), 1.0, 0.0,
+                         z_out=torch.zeros((4, 57, 65), dtype=torch.float64, device="cuda"))
+
+
+# ------------------------------------------------------- dictionary statistics
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_dict_stats_match_oracle(lib, dtype):
+    for pb, L in ((_small_image(15, P=2, L=(5, 6)), (5, 6)), (_small_signal(16), 32)):
+        Z = pb.Z_true
+        X = pb.X
+        if dtype == torch.float32:
+            Z = Z.astype(np.float32).astype(np.float64)
+            X = X.astype(np.float32).astype(np.float64)
+        ztz, ztx = lib.dicodile_dict_stats(dev(Z, dtype), dev(X, dtype), L)
+        phi, psi = oracle.dict_stats(Z, X, L)
+        tol = 1e-12 if dtype == torch.float64 else 1e-6
+        np.testing.assert_allclose(host(ztz), phi, rtol=0, atol=tol * max(1.0, np.abs(phi).max()))
+        np.testing.assert_allclose(host(ztx), psi, rtol=0, atol=tol * max(1.0, np.abs(psi).max()))
