@@ -24,6 +24,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1901_09235_amd", "csrc")
+
+
+def kernel_source_digest() -> str:
+    """Digest of the source that defines the round kernel: counter results are
+    only used while that kernel is unchanged."""
+    import hashlib
+    with open(os.path.join(CSRC, "dcdl_device.h"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def stored_traffic(workload: str):
+    """HBM bytes per launch of the round kernel from the committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE runs, if they were taken on the current sources."""
+    path = os.path.join(PROFILES, f"traffic_lgcd_rounds_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    return rec
 
 
 def parse():
@@ -32,13 +55,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="image_1024",
-                    choices=["image_1024", "signal_1d", "image_rgb_4096"])
+                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images"])
+    ap.add_argument("--batch-n", type=int, default=256, help="instances of the batch workload")
+    ap.add_argument("--plain", type=int, default=-1,
+                    help="batch workload: also time this many instances one solve per call "
+                         "(-1: all of them, 0: skip)")
     ap.add_argument("--size", type=int, default=0, help="override the image side (testing)")
     ap.add_argument("--grid", type=int, nargs="*", default=None)
     ap.add_argument("--tile", type=int, nargs="*", default=None)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128, help="side of the oracle's crop")
+    ap.add_argument("--probe-mib", type=int, default=1024, help="copy-probe size (0: skip)")
     return ap.parse_args()
 
 
@@ -83,8 +111,78 @@ def cpu_baseline(args, pb_full):
             "sweeps": info["n_sweeps"]}
 
 
+def run_batch(args):
+    """Batching pattern: n uneven images sharing a dictionary, solved in one
+    persistent launch per step, beside the plain form (one solve per call)."""
+    import numpy as np
+    import torch
+    import paper_1901_09235_amd as dl
+    from paper_1901_09235_amd import synth
+
+    t0 = time.perf_counter()
+    D_np, pbs = synth.batch_images(n=args.batch_n)
+    t_gen = time.perf_counter() - t0
+    D = torch.from_numpy(D_np).to("cuda", dtype=torch.float32).contiguous()
+    Xs = [torch.from_numpy(pb.X).to("cuda", dtype=torch.float32).contiguous() for pb in pbs]
+    lams = [pb.lambda_frac * dl.dicodile_lambda_max(X, D) for pb, X in zip(pbs, Xs)]
+    tols = [1e-5 * l for l in lams]
+    zs = [torch.empty((D.shape[0], X.shape[1] - D.shape[2] + 1, X.shape[2] - D.shape[3] + 1),
+                      dtype=torch.float32, device="cuda") for X in Xs]
+    bopts = {}
+    if args.threads:
+        bopts["threads"] = args.threads
+    if args.tile:
+        bopts["tile"] = tuple(args.tile) if len(args.tile) > 1 else args.tile[0]
+    for _ in range(args.warmup):
+        dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs, **bopts)
+    torch.cuda.synchronize()
+    binfos, t0 = [], time.perf_counter()
+    for _ in range(args.steps):
+        _, infos, binfo = dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs, **bopts)
+        binfos.append(binfo)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    if any(b["n_converged"] != len(pbs) for b in binfos):
+        raise SystemExit(f"batch did not converge: {binfos[-1]}")
+    n_plain = len(pbs) if args.plain < 0 else min(args.plain, len(pbs))
+    t_plain = None
+    plain_kkt = 0.0
+    if n_plain > 0:
+        t0 = time.perf_counter()
+        for X, z, lam, tol in list(zip(Xs, zs, lams, tols))[:n_plain]:
+            _, info = dl.dicodile_csc(X, D, lam, tol, z_out=z, max_rounds=50_000_000, timeout_s=120)
+            plain_kkt = max(plain_kkt, info["kkt"])
+            if info["status"] != "OK":
+                raise SystemExit(f"plain solve did not converge: {info}")
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / n_plain * len(pbs)
+    upd = binfos[-1]["n_updates"]
+    out = {
+        "metric": "CSC time-to-KKT-tol & coord updates/s; batched vs plain",
+        "value": len(pbs) / dt, "unit": "instances/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch_{len(pbs)}_images_128-1024_K16_L12", "dictionary": list(D.shape),
+                   "lambda": "0.1 lambda_max each", "tol": "1e-5 lambda each",
+                   "positions": int(sum((X.shape[1] - 11) * (X.shape[2] - 11) for X in Xs))},
+        "updates_per_s": upd / dt,
+        "max_kkt": max(i["kkt"] for i in infos),
+        "batched_phase_ms": {"setup": binfos[-1]["t_setup_s"] * 1e3, "rounds": binfos[-1]["t_rounds_s"] * 1e3,
+                             "check": binfos[-1]["t_check_s"] * 1e3},
+        "workers": binfos[-1]["workers"], "launches": binfos[-1]["n_passes"],
+        "used_graph": binfos[-1]["used_graph"],
+        "plain_s_for_all": t_plain,
+        "plain_instances_timed": n_plain,
+        "batched_over_plain": (t_plain / dt) if t_plain else None,
+        "generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "batch_images" and args.gpus == 1:
+        return run_batch(args)
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported by this build "
               "(each box has one MI355X and the solver has no multi-GPU path).", file=sys.stderr)
@@ -111,6 +209,14 @@ def main():
     if args.threads:
         opts["threads"] = args.threads
 
+    copy_gbs = None
+    if args.probe_mib > 0:
+        n = args.probe_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        sec = dl.dicodile_copy_probe(dst, src, repeats=5)
+        copy_gbs = 2 * n * 4 / sec / 1e9
+        del src, dst
     for _ in range(args.warmup):
         dl.dicodile_csc(X, D, lam, tol, z_out=z, **opts)
     torch.cuda.synchronize()
@@ -165,7 +271,15 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "lgcd_rounds", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None},
+        "hbm_copy_gbs": copy_gbs,
+        "worker_phase_us_per_round": {
+            k: last[f"t_worker_{k}_s"] / max(1, last["n_rounds"]) * 1e6
+            for k in ("wait", "select", "collect", "apply")},
     }
+    tr = stored_traffic(pb.name)
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["roofline"]["traffic_source"] = tr["source"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(args, pb)
     print(json.dumps(out), flush=True)

@@ -85,7 +85,7 @@ typedef struct {
   int32_t refresh_every;  /* recompute beta from its definition every this many sweeps
                              (drift correction, FP64 contraction); 0 -> only at the end */
   int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
-  int32_t reserved;
+  int32_t inner;          /* sub-domain visits per worker per round; 0 -> 1 */
   int64_t max_rounds;     /* cap on worker rounds (0 -> unlimited) */
   double div_guard;       /* stop with DCDL_EDIVERGED if |Z| exceeds this (0 -> off) */
   double timeout_s;       /* wall-clock cap for the whole call (0 -> none) */
@@ -171,6 +171,55 @@ int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void
  * Accumulation is in FP64 over the non-zeros of z. */
 int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, const void *z, const void *X,
                         void *ztz_out, void *ztX_out, void *stream);
+
+/* Batch-level options of dicodile_csc_batch.  Zero-initialise for defaults. */
+typedef struct {
+  int32_t no_graph;     /* 1: enqueue the per-instance set-up and check kernels directly
+                           instead of recording them as HIP graphs */
+  int32_t workers;      /* workgroups spread over the instances; 0 -> every co-resident slot */
+  int32_t threads;      /* threads per worker workgroup (64 ... 1024); 0 -> 256 */
+  int32_t tile[2];      /* sub-domain size; 0 -> 2 L_i (Sec. 3) */
+  int32_t max_polish;   /* extra passes for instances failing the final check; 0 -> 2 */
+  int32_t inner;        /* sub-domain visits per worker per round; 0 -> 1 */
+  int32_t reserved;
+} dcdl_batch_opts;
+
+/* Filled by dicodile_csc_batch when not NULL (host memory). */
+typedef struct {
+  double t_total_s;     /* wall time of the call */
+  double t_setup_s;     /* DtD, beta init and move caches of every instance */
+  double t_rounds_s;    /* the persistent round launch(es) */
+  double t_check_s;     /* FP64 checks and output transposes */
+  int64_t n_updates;    /* summed over instances */
+  int64_t workers;      /* workgroups of the first launch */
+  int32_t n_converged;  /* instances that passed the sweep certificate and the KKT target */
+  int32_t n_passes;     /* launches of the round kernel */
+  int32_t used_graph;   /* 1 if the set-up and check passes ran as HIP graphs */
+  int32_t reserved;
+} dcdl_batch_info;
+
+/* Solve n independent instances of eq. csc that share the dictionary D, in one
+ * persistent launch of the round kernel whose workgroups are spread over the
+ * instances (each instance runs its own worker grid, soft-lock rounds and
+ * stopping consensus, Alg. 3).  All shapes share ndim, P, K and L; only T
+ * differs.  X and z_out are host arrays of n device pointers; D is one device
+ * pointer; opts holds n per-instance options (lambda, tol, positive, certify,
+ * dtype, kkt_target; dtype must agree); infos (host, may be NULL) receives n
+ * records.  Returns DCDL_OK if every instance converged, DCDL_NOT_CONVERGED if
+ * some hit a cap (their z holds the iterate).  For callers that hold many
+ * small or medium solves at once: batching fills the chip where one solve at
+ * a time would not. */
+int dicodile_csc_batch(int32_t n, const dcdl_shape *shapes, const void *const *X, const void *D,
+                       const dcdl_csc_opts *opts, void *const *z_out, dcdl_csc_info *infos,
+                       const dcdl_batch_opts *bopts, dcdl_batch_info *binfo, void *stream);
+
+/* Streaming copy dst = src of `bytes` bytes (16-byte aligned, a multiple of
+ * 16), `repeats` times; *seconds (host, may be NULL) receives the average time
+ * of one copy measured with HIP events.  Reads + writes 2*bytes of HBM per
+ * copy: the achievable-bandwidth reference of the roofline figures and the
+ * calibration kernel of the traffic counters. */
+int dicodile_copy_probe(void *dst, const void *src, size_t bytes, int32_t repeats, double *seconds,
+                        void *stream);
 
 #ifdef __cplusplus
 }

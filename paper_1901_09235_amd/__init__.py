@@ -18,7 +18,8 @@ import os
 
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
            "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-           "dicodile_dict_stats", "dicodile_release", "STATUS"]
+           "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch", "dicodile_release",
+           "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "libdicodile_mi355x.so")
@@ -47,7 +48,7 @@ class CscOpts(ctypes.Structure):
                 ("threads", ctypes.c_int32), ("tile", ctypes.c_int32 * 2),
                 ("grid", ctypes.c_int32 * 2), ("warm_start", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("max_polish", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
+                ("inner", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
                 ("kkt_target", ctypes.c_double)]
 
@@ -92,8 +93,12 @@ def load():
     lib.dicodile_objective_kkt.argtypes = [sp, i32, vp, vp, vp, dbl, i32, ctypes.POINTER(dbl),
                                            ctypes.POINTER(dbl), vp]
     lib.dicodile_dict_stats.argtypes = [sp, i32, vp, vp, vp, vp, vp]
+    lib.dicodile_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(dbl), vp]
+    lib.dicodile_csc_batch.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p, vp]
     for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-              "dicodile_dict_stats"):
+              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -197,7 +202,7 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
-              div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False) -> CscOpts:
+              div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0) -> CscOpts:
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -211,6 +216,7 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
     o.warm_start, o.refresh_every, o.max_polish = int(warm_start), int(refresh_every), int(max_polish)
     o.max_rounds, o.div_guard, o.timeout_s = int(max_rounds), float(div_guard), float(timeout_s)
     o.kkt_target = float(kkt_target)
+    o.inner = int(inner)
     return o
 
 
@@ -292,3 +298,90 @@ def dicodile_dict_stats(z, X, L, stream=None):
                                    ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(ztz.data_ptr()),
                                    ctypes.c_void_p(ztX.data_ptr()), _stream(stream)))
     return ztz, ztX
+
+
+def dicodile_copy_probe(dst, src, repeats: int = 10, stream=None) -> float:
+    """Average seconds of one streaming copy dst <- src (device tensors of equal byte size)."""
+    lib = load()
+    _device_tensor(dst, "dst")
+    _device_tensor(src, "src")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise DicodileError(-1, "copy probe buffers differ in size")
+    out = ctypes.c_double(0.0)
+    _check(lib.dicodile_copy_probe(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                                   ctypes.c_size_t(nbytes), int(repeats), ctypes.byref(out),
+                                   _stream(stream)))
+    return out.value
+
+
+class BatchOpts(ctypes.Structure):
+    _fields_ = [("no_graph", ctypes.c_int32), ("workers", ctypes.c_int32),
+                ("threads", ctypes.c_int32), ("tile", ctypes.c_int32 * 2),
+                ("max_polish", ctypes.c_int32), ("inner", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("t_total_s", ctypes.c_double), ("t_setup_s", ctypes.c_double),
+                ("t_rounds_s", ctypes.c_double), ("t_check_s", ctypes.c_double),
+                ("n_updates", ctypes.c_int64), ("workers", ctypes.c_int64),
+                ("n_converged", ctypes.c_int32), ("n_passes", ctypes.c_int32),
+                ("used_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def dicodile_csc_batch(Xs, D, lams, tols, z_outs=None, stream=None, graph=True, workers=0,
+                       threads=0, tile=None, max_polish=0, inner=0, **opts):
+    """Solve len(Xs) instances sharing D in one persistent launch.
+
+    Xs: list of device tensors (P, T...) with the same P and ndim; lams, tols:
+    per-instance floats.  Per-instance keyword options (positive, certify,
+    kkt_target, no_soft_lock, div_guard) apply to every instance.  Returns
+    (z list, per-instance info list, batch info dict)."""
+    torch = _torch()
+    lib = load()
+    n = len(Xs)
+    if n == 0:
+        return [], [], {}
+    _device_tensor(D, "D")
+    code = _dtype_code(D)
+    shapes = (Shape * n)()
+    xp = (ctypes.c_void_p * n)()
+    zp = (ctypes.c_void_p * n)()
+    ol = (CscOpts * n)()
+    if z_outs is None:
+        z_outs = [None] * n
+    outs = []
+    for i, X in enumerate(Xs):
+        _device_tensor(X, f"X[{i}]")
+        if X.dtype != D.dtype:
+            raise DicodileError(-1, "every X must share D's dtype")
+        s = _shape(X, D)
+        shapes[i] = s
+        z = z_outs[i]
+        if z is None:
+            z = torch.empty(_zshape(s), dtype=X.dtype, device=X.device)
+        _device_tensor(z, f"z_out[{i}]")
+        if tuple(z.shape) != _zshape(s):
+            raise DicodileError(-1, f"z_out[{i}] must be {_zshape(s)}")
+        outs.append(z)
+        xp[i] = X.data_ptr()
+        zp[i] = z.data_ptr()
+        ol[i] = make_opts(lams[i], tols[i], code, **opts)
+    bo = BatchOpts()
+    bo.no_graph, bo.workers, bo.threads, bo.max_polish = int(not graph), int(workers), int(threads), int(max_polish)
+    bo.inner = int(inner)
+    if tile is not None:
+        t = (tile, 0) if isinstance(tile, int) else tuple(tile)
+        bo.tile[0], bo.tile[1] = int(t[0]), int(t[1])
+    infos = (CscInfo * n)()
+    bi = BatchInfo()
+    rc = lib.dicodile_csc_batch(ctypes.c_int32(n), ctypes.cast(shapes, ctypes.c_void_p),
+                                ctypes.cast(xp, ctypes.c_void_p), ctypes.c_void_p(D.data_ptr()),
+                                ctypes.cast(ol, ctypes.c_void_p), ctypes.cast(zp, ctypes.c_void_p),
+                                ctypes.cast(infos, ctypes.c_void_p), ctypes.cast(ctypes.byref(bo), ctypes.c_void_p),
+                                ctypes.cast(ctypes.byref(bi), ctypes.c_void_p), _stream(stream))
+    _check(rc, allow_not_converged=True)
+    il = [info_dict(infos[i], 0 if infos[i].converged else 1) for i in range(n)]
+    bd = {f: getattr(bi, f) for f, _ in BatchInfo._fields_ if f != "reserved"}
+    bd["status"] = STATUS.get(rc, rc)
+    return outs, il, bd

@@ -48,6 +48,7 @@ struct Buf {
 struct DeviceState {
   std::mutex mu;
   std::map<std::string, Buf> bufs;
+  hipStream_t aux = nullptr;  // library-owned stream (default priority) for captured work
   int cus = 0;
   bool checked = false;
   bool is_gfx950 = false;
@@ -173,42 +174,16 @@ int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, cons
   return DCDL_OK;
 }
 
-// FP64 residual res = X - Z*D from a position-major z; returns nnz and sum|z|.
+// FP64 residual res = X - Z*D of a position-major z, enqueued without host
+// synchronisation; acc[0] += sum |z|, acc[1] += nnz (acc must start at 0).
 template <class R>
-int residual64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const double *D64, const R *zpm,
-               double **res_out, long long *nnz_out, double *l1_out) {
-  const long long nx = (long long)g.P * g.T1 * g.T2, nz = (long long)g.H * g.W * g.KS;
-  double *res;
-  unsigned long long *cnt;
-  double *l1;
-  WS("res64", sizeof(double) * nx, res);
-  WS("nzcount", 64, cnt);
-  l1 = reinterpret_cast<double *>(cnt + 1);
+int residual64_async(hipStream_t stream, const Geom &g, const R *X, const double *D64, const R *zpm, double *res,
+                     double *acc) {
+  const long long nx = (long long)g.P * g.T1 * g.T2, HW = (long long)g.H * g.W;
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, res);
-  HIPCK(hipMemsetAsync(cnt, 0, 16, stream));
-  hipLaunchKernelGGL(collect_nonzeros<R>, dim3(grid_stride_blocks(nz)), dim3(256), 0, stream, nz, g.KS, zpm, cnt,
-                     (NzEntry *)nullptr, 0ull, l1);
+  const unsigned nb = (unsigned)std::min<long long>((HW + 3) / 4, 65536);
+  hipLaunchKernelGGL((residual_dense<R, double>), dim3(nb), dim3(256), 0, stream, g, zpm, D64, res, acc);
   HIPCK(hipGetLastError());
-  unsigned long long hc[2];
-  HIPCK(hipMemcpyAsync(hc, cnt, 16, hipMemcpyDeviceToHost, stream));
-  HIPCK(hipStreamSynchronize(stream));
-  const unsigned long long n = hc[0];
-  double l1v;
-  std::memcpy(&l1v, &hc[1], sizeof(double));
-  if (n > 0) {
-    NzEntry *list;
-    WS("nzlist", sizeof(NzEntry) * n, list);
-    HIPCK(hipMemsetAsync(cnt, 0, 8, stream));
-    hipLaunchKernelGGL(collect_nonzeros<R>, dim3(grid_stride_blocks(nz)), dim3(256), 0, stream, nz, g.KS, zpm, cnt,
-                       list, n, (double *)nullptr);
-    const long long nb = (long long)n < 65536 ? (long long)n : 65536;
-    hipLaunchKernelGGL(scatter_atoms<double>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, (long long)n, D64,
-                       res);
-    HIPCK(hipGetLastError());
-  }
-  *res_out = res;
-  *nnz_out = (long long)n;
-  *l1_out = l1v;
   return DCDL_OK;
 }
 
@@ -217,17 +192,15 @@ int residual64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, c
 template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
             int positive, double *obj, double *kkt, long long *nnz) {
-  const long long nd = (long long)g.K * g.P * g.L1 * g.L2;
+  const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
+  WS("res64", sizeof(double) * nx, res);
   WS("scal", 64, scal);
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
-  long long n = 0;
-  double l1 = 0;
-  int rc = residual64<R>(ds, stream, g, X, D64, zpm, &res, &n, &l1);
+  HIPCK(hipMemsetAsync(scal, 0, 32, stream));
+  int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2);
   if (rc) return rc;
-  HIPCK(hipMemsetAsync(scal, 0, 16, stream));
-  const long long nx = (long long)g.P * g.T1 * g.T2;
   hipLaunchKernelGGL(sum_squares, dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res, scal);
   CorrOut o{};
   o.zpm = zpm;
@@ -236,12 +209,12 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.result = scal + 1;
   rc = run_corr<double, double, R, CORR_KKT>(stream, g, res, D64, o);
   if (rc) return rc;
-  double h[2];
-  HIPCK(hipMemcpyAsync(h, scal, 16, hipMemcpyDeviceToHost, stream));
+  double h[4];
+  HIPCK(hipMemcpyAsync(h, scal, 32, hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
-  if (obj) *obj = 0.5 * h[0] + lambda * l1;
+  if (obj) *obj = 0.5 * h[0] + lambda * h[2];
   if (kkt) *kkt = h[1] / lambda;
-  if (nnz) *nnz = n;
+  if (nnz) *nnz = (long long)h[3];
   return DCDL_OK;
 }
 
@@ -252,16 +225,15 @@ template <class R>
 int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
                   const double *nrm64, R *beta, bool fresh) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
-  double *D64, *res;
+  double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
+  WS("res64", sizeof(double) * nx, res);
   if (fresh) {
+    WS("scal", 64, scal);
     hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
-    long long n = 0;
-    double l1 = 0;
-    int rc = residual64<R>(ds, stream, g, X, D64, zpm, &res, &n, &l1);
+    HIPCK(hipMemsetAsync(scal, 0, 32, stream));
+    int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2);
     if (rc) return rc;
-  } else {
-    WS("res64", sizeof(double) * nx, res);
   }
   CorrOut ob{};
   ob.beta = beta;
@@ -337,7 +309,7 @@ int plan_grid(const Geom &g, int ndim, const dcdl_csc_opts *o, int cap, Plan *p)
   const int ext1 = (g.H + W1 - 1) / W1, ext2 = (g.W + W2 - 1) / W2;
   p->W1 = W1;
   p->W2 = W2;
-  p->mmax = ((ext1 + p->tile1 - 1) / p->tile1) * ((ext2 + p->tile2 - 1) / p->tile2);
+  p->mmax = std::max(1, (ext1 + p->tile1 / 2) / p->tile1) * std::max(1, (ext2 + p->tile2 / 2) / p->tile2);
   return DCDL_OK;
 }
 
@@ -444,6 +416,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   hi.tile1 = pl.tile1;
   hi.tile2 = pl.tile2;
   hi.mmax = pl.mmax;
+  hi.inner = o->inner > 0 ? o->inner : 1;
   hi.wg_base = 0;
   hi.positive = o->positive;
   hi.certify = o->certify;
@@ -617,6 +590,10 @@ int dicodile_release(void) {
   for (auto &kv : ds->bufs)
     if (kv.second.p) HIPCK(hipFree(kv.second.p));
   ds->bufs.clear();
+  if (ds->aux) {
+    HIPCK(hipStreamDestroy(ds->aux));
+    ds->aux = nullptr;
+  }
   return DCDL_OK;
 }
 
@@ -726,6 +703,30 @@ int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void
   return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
 }
 
+int dicodile_copy_probe(void *dst, const void *src, size_t bytes, int32_t repeats, double *seconds,
+                        void *stream_) {
+  if (!dst || !src || bytes == 0 || (bytes & 15) || ((uintptr_t)dst & 15) || ((uintptr_t)src & 15) || repeats < 1)
+    return fail(DCDL_EINVAL, "copy probe needs 16-byte aligned, non-empty buffers and repeats >= 1");
+  PROLOGUE();
+  const long long n16 = (long long)(bytes / 16);
+  const unsigned nb = (unsigned)std::min<long long>((n16 + 255) / 256, (long long)ds->cus * 16);
+  hipEvent_t e0, e1;
+  HIPCK(hipEventCreate(&e0));
+  HIPCK(hipEventCreate(&e1));
+  HIPCK(hipEventRecord(e0, stream));
+  for (int i = 0; i < repeats; ++i)
+    hipLaunchKernelGGL(copy_probe, dim3(nb), dim3(256), 0, stream, n16, (const uint4 *)src, (uint4 *)dst);
+  HIPCK(hipGetLastError());
+  HIPCK(hipEventRecord(e1, stream));
+  HIPCK(hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (seconds) *seconds = ms * 1e-3 / repeats;
+  return DCDL_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -810,3 +811,4 @@ extern "C" int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, co
                                    (double *)ztX_out);
   return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
 }
+#include "batch.inc"

@@ -59,7 +59,7 @@ __host__ __device__ inline int atom_stride(int K, int elem_bytes) {
 }
 
 // Per-instance control block, followed in memory by two rings of kRing ints
-// (sweep completion counts and sweep activity flags).
+// (per-round completion counts and per-round quiet counts).
 struct Ctl {
   int32_t converged;
   int32_t stop;
@@ -80,6 +80,7 @@ template <class R> struct Inst {
   int K, KS, L1, L2, U1, U2;
   int H, W;
   int W1, W2, tile1, tile2, mmax, wg_base;
+  int inner;  // sub-domain visits per round (at most Mw); 0 -> 1
   int positive, certify, soft_lock, pad0;
   R lambda, tol, div_guard;
   long long max_rounds;
@@ -272,35 +273,133 @@ __device__ __forceinline__ int block_or(int v, int *sh) {
 }
 
 // ------------------------------------------------------------- the round kernel
-//
+
+template <class R, int NT> struct PatchCtx {
+  R *sh_ps;
+  uint16_t *sh_pk;
+  const R *sh_inv_n;
+  int G, spl, sq, pl0, q0;
+};
+
+// Applies one accepted update (atom ck at position (ch, cw0), change delta) to
+// rows [r1, r2) x columns [c1, c2) of this worker's region: beta -= A * delta
+// (eq. beta_update; beta at the updated coordinate itself is unchanged), then
+// recomputes the best-move cache of the patched positions.  Every thread of
+// the workgroup takes part; the region must lie inside the worker's domain.
+template <class R, int NT>
+__device__ __forceinline__ void patch_region(const Inst<R> &I, const PatchCtx<R, NT> &P, int r1, int r2, int c1,
+                                             int c2, int ck, int ch, int cw0, R delta) {
+  constexpr int LBUF = 4096;
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  const int tid = threadIdx.x;
+  const int K = I.K, KS = I.KS, W = I.W, G = P.G;
+  const int nc = c2 - c1;
+  const int cw = min(nc, LBUF / G);
+  const int rc = max(1, LBUF / (cw * G));
+  const int cg = ck / VE, ce = ck - cg * VE;
+  for (int rr0 = r1; rr0 < r2; rr0 += rc) {
+    const int rr1 = min(rr0 + rc, r2);
+    for (int cc0 = c1; cc0 < c2; cc0 += cw) {
+      const int ccw = min(cw, c2 - cc0);
+      const int ng = ccw * G;
+      for (int rr = rr0; rr < rr1; ++rr) {
+        V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
+        const V *__restrict__ arow = reinterpret_cast<const V *>(
+            I.A + (((long long)ck * I.U1 + (rr - ch + I.L1 - 1)) * I.U2 + (cc0 - cw0 + I.L2 - 1)) * KS);
+        const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
+        const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
+        const int gself = (rr == ch && cw0 >= cc0 && cw0 < cc0 + ccw) ? (cw0 - cc0) * G + cg : -1;
+        R *prow = P.sh_ps + (rr - rr0) * ng;
+        uint16_t *krow = P.sh_pk + (rr - rr0) * ng;
+        int pl = P.pl0, qq = P.q0;
+#pragma unroll 4
+        for (int j = tid; j < ng; j += NT) {
+          V b = brow[j];
+          const V av = arow[j];
+          const uint32_t mt = mrow[pl];
+          const V bold = b;
+          b = Vec<R>::fma_neg(b, av, delta);
+          if (j == gself) Vec<R>::set(b, ce, Vec<R>::get(bold, ce));  // beta at (k0, w0) is unchanged
+          brow[j] = b;
+          const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
+          R best = R(-1);
+          int bk = 0;
+#pragma unroll
+          for (int e = 0; e < VE; ++e) {
+            const int k = qq * VE + e;
+            const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
+            const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
+            if (sc > best) {
+              best = sc;
+              bk = k;
+            }
+          }
+          prow[j] = best;
+          krow[j] = (uint16_t)bk;
+          qq += P.sq;
+          pl += P.spl;
+          if (qq >= G) {
+            qq -= G;
+            pl += 1;
+          }
+        }
+      }
+      __syncthreads();
+      const int npos = (rr1 - rr0) * ccw;
+      for (int t = tid; t < npos; t += NT) {
+        const int rr = rr0 + t / ccw, pl = t % ccw;
+        const int pos = rr * W + cc0 + pl;
+        const R *pp = P.sh_ps + t * G;
+        const uint16_t *pk = P.sh_pk + t * G;
+        R best = pp[0];
+        int bk = pk[0];
+        for (int g = 1; g < G; ++g)
+          if (pp[g] > best) {
+            best = pp[g];
+            bk = pk[g];
+          }
+        score_st(I.score + pos, best);
+        I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // One workgroup is one worker of Alg. 3 (DiCoDiLe-Z).  Worker w of an instance
 // owns S_w, a block of a W1 x W2 balanced split of the valid domain, cut into
-// sub-domains of tile1 x tile2 positions.  Round r visits sub-domain
-// (r mod mmax) and runs two phases:
-//   A  select the best move of the sub-domain from M (Alg. 1's local greedy
-//      choice), test it against the scores of the other workers' positions
-//      in its neighbourhood V(w0) (eq. soft_lock, lower worker index wins a
-//      tie) and publish the candidate (accepted or "none"), tagged with r;
-//   B  every worker applies, to the part of beta, z and M it owns, the
-//      accepted candidates of itself and of its grid neighbours whose
-//      neighbourhood meets S_w (eq. beta_update), in increasing worker order,
-//      then publishes progress r + 1.
-// Phase A of round r reads the border of S_w's neighbours, which only they
-// write, in their phase B: it starts once each neighbour's progress is >= r.
-// A neighbour starts its phase B of round r only after it has read this
-// worker's round-r candidate, which is published after this worker's phase A
-// reads.  Worker sizes of at least L_i keep every interaction between grid
-// neighbours.
+// Mw balanced sub-domains of about tile1 x tile2 positions that it visits
+// cyclically.
 //
-// Stopping: a sweep is mmax rounds.  A sweep in which no worker found a move
-// scoring >= tol leaves the iterate unchanged, so every worker then exits.
+// Neighbours read the scores of S_w's border band (positions within L_i - 1
+// of a side shared with a neighbour) in their soft-lock tests.  A round runs:
+//   A  visit `inner` sub-domains (Alg. 1's local greedy choice).  Candidates
+//      whose patch stays clear of the band concern no other worker
+//      (eq. soft_lock only applies near the border): they are applied at once.
+//      The first band-reaching candidate is held; it is tested against the
+//      other workers' scores in V(w0) when V(w0) leaves S_w (eq. soft_lock,
+//      lower worker index wins a tie) and published, tagged with the round;
+//   B  every worker applies, to the part of beta, z and the cache it owns, the
+//      accepted published candidates of itself and of its grid neighbours
+//      whose neighbourhood meets S_w (eq. beta_update), in increasing worker
+//      order, then publishes progress r + 1.
+// Phase A of round r reads the band of S_w's neighbours, which only they
+// write, in their phase B: it starts once each neighbour's progress is >= r.
+// A neighbour starts its phase B of round r only after reading this worker's
+// round-r candidate, published after this worker's phase A reads.  Worker
+// sizes of at least L_i keep every interaction between grid neighbours.
+//
+// Stopping: a worker is quiet once its last Mw visits found no move scoring
+// >= tol and no patch touched S_w since.  When every worker reports quiet at
+// the end of the same round, every coordinate's move is below tol and no
+// further update can happen: all workers exit.
 template <class R, int NT>
 __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ insts,
                                                    const int *__restrict__ wg_inst,
                                                    long long timeout_ticks) {
-  constexpr int LBUF = 4096;  // partial maxima per LDS chunk
+  constexpr int LBUF = 4096;
   constexpr int NWAVE = NT / 64;
-  typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
   __shared__ R sh_ps[LBUF];
   __shared__ uint16_t sh_pk[LBUF];
@@ -310,7 +409,8 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
   __shared__ int sh_exit;
   __shared__ int sh_wait;
   __shared__ int sh_cok;
-  __shared__ R sh_znew;
+  __shared__ int sh_k0;
+  __shared__ R sh_d;
   __shared__ unsigned long long sh_tag[9];
   __shared__ R sh_delta[9];
   __shared__ int sh_nbr[9];
@@ -324,12 +424,26 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
   const int K = I.K, H = I.H, W = I.W;
   const int a1 = part_start(wi, H, I.W1), b1 = part_start(wi + 1, H, I.W1);
   const int a2 = part_start(wj, W, I.W2), b2 = part_start(wj + 1, W, I.W2);
-  const int nb1 = (b1 - a1 + I.tile1 - 1) / I.tile1, nb2 = (b2 - a2 + I.tile2 - 1) / I.tile2;
+  // sub-domains: about extent / tile per axis, balanced (sizes differ by <= 1)
+  const int ext1 = b1 - a1, ext2 = b2 - a2;
+  const int nb1 = max(1, (ext1 + I.tile1 / 2) / I.tile1), nb2 = max(1, (ext2 + I.tile2 / 2) / I.tile2);
   const int Mw = nb1 * nb2;
-  const int KS = I.KS;
-  const int G = KS / VE;  // vectors per position
+  const int inner = I.inner > 0 ? min(I.inner, Mw) : 1;
+  // candidates at w0 in [in_lo, in_hi[ patch nothing of the band neighbours read
+  const int in_lo1 = wi > 0 ? a1 + 2 * (I.L1 - 1) : a1, in_hi1 = wi < I.W1 - 1 ? b1 - 2 * (I.L1 - 1) : b1;
+  const int in_lo2 = wj > 0 ? a2 + 2 * (I.L2 - 1) : a2, in_hi2 = wj < I.W2 - 1 ? b2 - 2 * (I.L2 - 1) : b2;
 
-  for (int k = tid; k < KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
+  PatchCtx<R, NT> P;
+  P.sh_ps = sh_ps;
+  P.sh_pk = sh_pk;
+  P.sh_inv_n = sh_inv_n;
+  P.G = I.KS / VE;
+  P.spl = NT / P.G;
+  P.sq = NT - P.spl * P.G;
+  P.pl0 = tid / P.G;
+  P.q0 = tid - P.pl0 * P.G;
+
+  for (int k = tid; k < I.KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
   if (tid == 0) {
     int nn = 0;
     for (int di = -1; di <= 1; ++di)
@@ -347,13 +461,11 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
     nbr[q] = sh_nbr[q];
     nn += nbr[q] >= 0;
   }
-  // per-thread stepping of the flattened (position, vector) index by NT
-  const int spl = NT / G, sq = NT - (NT / G) * G;
-  const int pl0 = tid / G, q0 = tid - (tid / G) * G;
 
   unsigned long long my_upd = 0, my_cand = 0, my_lock = 0, my_visit = 0, my_chk = 0, my_patch = 0;
   unsigned long long tk_wait = 0, tk_sel = 0, tk_col = 0, tk_app = 0, tk_mark = 0;
-  int my_active = 0;
+  long long cursor = 0;  // visits so far
+  int quiet = 0;         // consecutive visits with no move >= tol and no patch of S_w
   const unsigned long long t_launch = __builtin_amdgcn_s_memrealtime();
   int r = 0;
   int exit_status = 0;
@@ -373,10 +485,10 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
       }
       sh_exit = f;
       sh_cok = 1;
+      tk_mark = __builtin_amdgcn_s_memrealtime();
     }
     __syncthreads();
     if (sh_exit) break;
-    if (tid == 0) tk_mark = __builtin_amdgcn_s_memrealtime();
     if (!wait_progress(I.prog, nbr, nn, w, r, timeout_ticks, &sh_wait)) {
       exit_status = 3;
       break;
@@ -387,33 +499,90 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
       tk_mark = t;
     }
 
-    // ---- phase A: locally greedy candidate of sub-domain m (Alg. 3, selection)
-    const int m = r % I.mmax;
+    // ---- phase A: `inner` visits.  Interior candidates are applied at once;
+    // the first band-reaching candidate is held for the protocol, and later
+    // interior candidates are applied only if neither lies in the other's
+    // V (they cannot interact); other candidates wait for the next cycle.
     R bs = R(-1);
     int bp = 0x7fffffff;
-    if (m < Mw) {
+    bool has = false;
+    int hh0 = 0, hw0 = 0;
+    long long restart = -1;  // first visit whose candidate had to wait: next round starts there
+    for (int v = 0; v < inner; ++v) {
+      const long long visit = cursor;
+      const int m = (int)(cursor % Mw);
+      ++cursor;
       ++my_visit;
       const int bi = m / nb2, bj = m - (m / nb2) * nb2;
-      const int s1 = a1 + bi * I.tile1, e1 = min(s1 + I.tile1, b1);
-      const int s2 = a2 + bj * I.tile2, e2 = min(s2 + I.tile2, b2);
+      const int s1 = a1 + part_start(bi, ext1, nb1), e1 = a1 + part_start(bi + 1, ext1, nb1);
+      const int s2 = a2 + part_start(bj, ext2, nb2), e2 = a2 + part_start(bj + 1, ext2, nb2);
       const int bw = e2 - s2, np = (e1 - s1) * bw;
+      R vs = R(-1);
+      int vp = 0x7fffffff;
       for (int t = tid; t < np; t += NT) {
         const int hh = s1 + t / bw, ww = s2 + t % bw;
         const int pos = hh * W + ww;
         const R sc = score_ld(I.score + pos);
-        if (sc > bs || (sc == bs && pos < bp)) {
-          bs = sc;
-          bp = pos;
+        if (sc > vs || (sc == vs && pos < vp)) {
+          vs = sc;
+          vp = pos;
         }
       }
+      block_argmax<R, NT>(vs, vp, sh_rs, sh_ri);
+      if (!(vs >= I.tol && vs > R(0))) {
+        ++quiet;
+        continue;
+      }
+      quiet = 0;
+      ++my_cand;
+      const int h0 = vp / W, w0 = vp - (vp / W) * W;
+      // with one visit per round every candidate takes the published path, so
+      // its patch runs in phase B beside the neighbours' ones
+      const bool interior = inner > 1 && h0 >= in_lo1 && h0 < in_hi1 && w0 >= in_lo2 && w0 < in_hi2;
+      if (!interior) {
+        if (!has) {
+          has = true;
+          bs = vs;
+          bp = vp;
+          hh0 = h0;
+          hw0 = w0;
+        } else if (restart < 0) {
+          restart = visit;  // a second band-reaching candidate waits for the next round
+        }
+        continue;
+      }
+      if (has && abs(h0 - hh0) < I.L1 && abs(w0 - hw0) < I.L2) {  // would interact with the held one
+        if (restart < 0) restart = visit;
+        continue;
+      }
+      if (tid == 0) {
+        const int k0 = meta_argk(I.meta[vp]);
+        const long long i0 = (long long)vp * I.KS + k0;
+        const R zc = I.z[i0];
+        const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+        I.z[i0] = zn;
+        const uint32_t mt = I.meta[vp];
+        I.meta[vp] = meta_pack(meta_argk(mt), meta_nzc(mt) + (zn != R(0)) - (zc != R(0)));
+        sh_k0 = k0;
+        sh_d = zn - zc;
+        if (I.div_guard > R(0) && (zn > I.div_guard || -zn > I.div_guard)) {
+          st_shared_i32(&I.ctl->stop, 1);
+          atomicCAS(&I.ctl->status, 0, 2);
+        }
+        wait_vm();
+      }
+      __syncthreads();
+      ++my_upd;
+      my_patch += (unsigned long long)(min(h0 + I.L1, b1) - max(h0 - I.L1 + 1, a1)) *
+                  (min(w0 + I.L2, b2) - max(w0 - I.L2 + 1, a2));
+      patch_region<R, NT>(I, P, max(h0 - I.L1 + 1, a1), min(h0 + I.L1, b1), max(w0 - I.L2 + 1, a2),
+                          min(w0 + I.L2, b2), sh_k0, h0, w0, sh_d);
     }
-    block_argmax<R, NT>(bs, bp, sh_rs, sh_ri);
-    const bool has = bs >= I.tol && bs > R(0);
-    int h0 = 0, w0 = 0, k0 = -1;
+    if (restart >= 0) cursor = restart;
+    int h0 = 0, w0 = 0;
     if (has) {
       h0 = bp / W;
       w0 = bp - h0 * W;
-      my_active = 1;
     }
     int locked = 0;
     if (has && I.soft_lock &&
@@ -437,23 +606,25 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
       }
       locked = block_or<NT>(lk, sh_ri);
     }
-    // the halo reads above must be complete before the candidate is visible
+    // the band reads above are complete before the candidate becomes visible
     wait_vm();
     __syncthreads();
     if (tid == 0) {
       unsigned long long tag = cand_tag(r, 0, kNoPos);
       unsigned long long dbits = 0;
       if (has) {
-        ++my_cand;
         if (locked) {
           ++my_lock;
         } else {
-          k0 = meta_argk(I.meta[bp]);
+          const int k0 = meta_argk(I.meta[bp]);
           const long long i0 = (long long)bp * I.KS + k0;
           const R zc = I.z[i0];
           const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+          // z and its non-zero count change now; beta and the cache in phase B
+          I.z[i0] = zn;
+          const uint32_t mt = I.meta[bp];
+          I.meta[bp] = meta_pack(meta_argk(mt), meta_nzc(mt) + (zn != R(0)) - (zc != R(0)));
           dbits = delta_bits<R>(zn - zc);
-          sh_znew = zn;
           tag = cand_tag(r, k0, (unsigned)bp);
           ++my_upd;
           if (I.div_guard > R(0) && (zn > I.div_guard || -zn > I.div_guard)) {
@@ -505,127 +676,37 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
       tk_mark = t;
     }
 
-    // ---- phase B: apply accepted updates that touch S_w (eq. beta_update)
+    // ---- phase B: apply accepted candidates that touch S_w (eq. beta_update)
     for (int q = 0; q < nn; ++q) {
       const unsigned long long tg = sh_tag[q];
       const unsigned cpos = tag_pos(tg);
       if (cpos == kNoPos) continue;
-      const int ck = tag_k0(tg);
       const int ch = (int)(cpos / (unsigned)W), cw0 = (int)(cpos - (unsigned)ch * (unsigned)W);
-      const R delta = sh_delta[q];
       const int r1 = max(ch - I.L1 + 1, a1), r2 = min(ch + I.L1, b1);
       const int c1 = max(cw0 - I.L2 + 1, a2), c2 = min(cw0 + I.L2, b2);
       if (r1 >= r2 || c1 >= c2) continue;
-      if (nbr[q] == w && tid == 0) {
-        const long long i0 = (long long)cpos * KS + ck;
-        const R zold = I.z[i0];
-        const R znew = sh_znew;
-        I.z[i0] = znew;
-        const uint32_t mt = I.meta[cpos];
-        I.meta[cpos] = meta_pack(meta_argk(mt), meta_nzc(mt) + (znew != R(0)) - (zold != R(0)));
-        wait_vm();
-      }
-      __syncthreads();
-      const int nc = c2 - c1;
-      my_patch += (unsigned long long)(r2 - r1) * nc;
-      const int cw = min(nc, LBUF / G);
-      const int rc = max(1, LBUF / (cw * G));
-      const int cg = ck / VE, ce = ck - cg * VE;
-      for (int rr0 = r1; rr0 < r2; rr0 += rc) {
-        const int rr1 = min(rr0 + rc, r2);
-        for (int cc0 = c1; cc0 < c2; cc0 += cw) {
-          const int ccw = min(cw, c2 - cc0);
-          const int ng = ccw * G;
-          for (int rr = rr0; rr < rr1; ++rr) {
-            V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
-            const V *__restrict__ arow = reinterpret_cast<const V *>(
-                I.A + (((long long)ck * I.U1 + (rr - ch + I.L1 - 1)) * I.U2 + (cc0 - cw0 + I.L2 - 1)) * KS);
-            const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
-            const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
-            const int gself = (rr == ch && cw0 >= cc0 && cw0 < cc0 + ccw) ? (cw0 - cc0) * G + cg : -1;
-            R *prow = sh_ps + (rr - rr0) * ng;
-            uint16_t *krow = sh_pk + (rr - rr0) * ng;
-            int pl = pl0, qq = q0;
-#pragma unroll 4
-            for (int j = tid; j < ng; j += NT) {
-              V b = brow[j];
-              const V av = arow[j];
-              const uint32_t mt = mrow[pl];
-              const V bold = b;
-              b = Vec<R>::fma_neg(b, av, delta);
-              if (j == gself) Vec<R>::set(b, ce, Vec<R>::get(bold, ce));  // beta at (k0, w0) is unchanged
-              brow[j] = b;
-              const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
-              R best = R(-1);
-              int bk = 0;
-#pragma unroll
-              for (int e = 0; e < VE; ++e) {
-                const int k = qq * VE + e;
-                const R zn = st_target(Vec<R>::get(b, e), I.lambda, sh_inv_n[k], I.positive);
-                const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
-                if (sc > best) {
-                  best = sc;
-                  bk = k;
-                }
-              }
-              prow[j] = best;
-              krow[j] = (uint16_t)bk;
-              qq += sq;
-              pl += spl;
-              if (qq >= G) {
-                qq -= G;
-                pl += 1;
-              }
-            }
-          }
-          __syncthreads();
-          const int npos = (rr1 - rr0) * ccw;
-          for (int t = tid; t < npos; t += NT) {
-            const int rr = rr0 + t / ccw, pl = t % ccw;
-            const int pos = rr * W + cc0 + pl;
-            const R *pp = sh_ps + t * G;
-            const uint16_t *pk = sh_pk + t * G;
-            R best = pp[0];
-            int bk = pk[0];
-            for (int g = 1; g < G; ++g)
-              if (pp[g] > best) {
-                best = pp[g];
-                bk = pk[g];
-              }
-            score_st(I.score + pos, best);
-            I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
-          }
-          __syncthreads();
-        }
-      }
+      quiet = 0;
+      my_patch += (unsigned long long)(r2 - r1) * (c2 - c1);
+      patch_region<R, NT>(I, P, r1, r2, c1, c2, tag_k0(tg), ch, cw0, sh_delta[q]);
     }
-    // score stores complete before the progress counter moves
+    // cache stores complete before the progress counter moves
     wait_vm();
     __syncthreads();
     if (tid == 0) {
       st_shared_i32(I.prog + w, r + 1);
       tk_app += __builtin_amdgcn_s_memrealtime() - tk_mark;
-    }
-
-    // ---- sweep bookkeeping and the global stopping consensus
-    if ((r + 1) % I.mmax == 0) {
-      if (tid == 0) {
-        const int s = r / I.mmax;
-        const int slot = s % kRing;
-        int *done = I.ring, *active = I.ring + kRing;
-        // the activity count lands before the completion count that reports it
-        if (my_active) __hip_atomic_fetch_add(&active[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        wait_vm();
-        const int old = __hip_atomic_fetch_add(&done[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (old == nW - 1) {
-          const int act = ld_shared_i32(&active[slot]);
-          st_shared_i32(&active[slot], 0);
-          st_shared_i32(&done[slot], 0);
-          atomicMax(&I.ctl->sweeps_done, s + 1);
-          if (act == 0) st_shared_i32(&I.ctl->converged, 1);
-        }
+      // ---- stopping consensus: quiet counts of round r
+      const int slot = r % kRing;
+      int *done = I.ring, *qcount = I.ring + kRing;
+      if (quiet >= Mw) __hip_atomic_fetch_add(&qcount[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      wait_vm();
+      const int old = __hip_atomic_fetch_add(&done[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (old == nW - 1) {
+        const int nq = ld_shared_i32(&qcount[slot]);
+        st_shared_i32(&qcount[slot], 0);
+        st_shared_i32(&done[slot], 0);
+        if (nq == nW) st_shared_i32(&I.ctl->converged, 1);
       }
-      my_active = 0;
     }
   }
   // ---- leave: neighbours must never wait on a finished worker
@@ -647,6 +728,7 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
     atomicAdd(&I.ctl->tk_collect, tk_col);
     atomicAdd(&I.ctl->tk_apply, tk_app);
     atomicMax(&I.ctl->max_round, r);
+    atomicMax(&I.ctl->sweeps_done, (int)(cursor / Mw));
     st_shared_i32(I.prog + w, 0x7fffffff);
   }
 }

@@ -282,6 +282,56 @@ __global__ __launch_bounds__(256) void sum_squares(long long n, const double *__
   if (threadIdx.x == 0) atomic_add_f64(out, a);
 }
 
+// res -= Z*D for a position-major z (atom stride KS), one wave per position:
+// the lanes find the non-zero atoms of the position, then scatter each one's
+// shifted atom (eq. model) with FP64 atomics.  Also accumulates sum |z| and
+// the non-zero count into acc[0], acc[1] (doubles).  No host round trip.
+template <class R, class Rd>
+__global__ __launch_bounds__(256) void residual_dense(Geom g, const R *__restrict__ z, const Rd *__restrict__ D,
+                                                      double *__restrict__ res, double *__restrict__ acc) {
+  __shared__ double sh[4];
+  const int lane = threadIdx.x & 63;
+  const long long HW = (long long)g.H * g.W;
+  const int PL = g.P * g.L1 * g.L2, LL = g.L1 * g.L2;
+  const long long plane = (long long)g.T1 * g.T2;
+  double l1 = 0.0, cnt = 0.0;
+  for (long long pos = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); pos < HW; pos += (long long)gridDim.x * 4) {
+    const int h = (int)(pos / g.W), w = (int)(pos - (pos / g.W) * g.W);
+    for (int kb = 0; kb < g.K; kb += 64) {
+      const int k = kb + lane;
+      const R v = k < g.K ? z[pos * g.KS + k] : R(0);
+      unsigned long long m = __ballot(v != R(0));
+      if (v != R(0)) {
+        l1 += fabs((double)v);
+        cnt += 1.0;
+      }
+      while (m) {
+        const int src = __ffsll((long long)m) - 1;
+        m &= m - 1;
+        const double zv = (double)__shfl(v, src, 64);
+        const Rd *dk = D + (long long)(kb + src) * PL;
+        for (int i = lane; i < PL; i += 64) {
+          const int p = i / LL, r = i - p * LL;
+          const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
+          atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -zv * (double)dk[i]);
+        }
+      }
+    }
+  }
+  l1 = block_sum<256>(l1, sh);
+  cnt = block_sum<256>(cnt, sh);
+  if (threadIdx.x == 0) {
+    atomic_add_f64(acc, l1);
+    atomic_add_f64(acc + 1, cnt);
+  }
+}
+
+// Fills n 32-bit words with a value (a kernel, so it may sit in a captured graph).
+__global__ __launch_bounds__(256) void fill_u32(long long n, uint32_t v, uint32_t *__restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = v;
+}
+
 // ------------------------------------------------------- dictionary stats
 // psi[k][p][t] += sum over the non-zeros of atom k in [beg, end) of z X_p[pos + t].
 // One workgroup per chunk; every chunk holds non-zeros of a single atom.
@@ -380,6 +430,14 @@ __global__ __launch_bounds__(256) void list_per_atom(int HW, int K, const R *__r
       list[slot] = e;
     }
   }
+}
+
+// ------------------------------------------------------- bandwidth probe
+// dst = src, 16 bytes per thread per step: a plain streaming copy used to
+// measure achievable HBM bandwidth and to calibrate traffic counters.
+__global__ __launch_bounds__(256) void copy_probe(long long n16, const uint4 *__restrict__ src, uint4 *__restrict__ dst) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n16; i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
 }
 
 }  // namespace dcdl

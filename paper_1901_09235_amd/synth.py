@@ -26,7 +26,9 @@ class Problem:
     name: str
     X: np.ndarray            # (P, T) or (P, T1, T2), float64
     D: np.ndarray            # (K, P, L) or (K, P, L1, L2), float64, unit-norm atoms
-    Z_true: np.ndarray       # (K, T-L+1) or (K, T1-L1+1, T2-L2+1), float64
+    z_index: np.ndarray      # flat indices of the non-zero activations in zshape
+    z_value: np.ndarray      # their values
+    zshape: tuple            # (K, T-L+1) or (K, T1-L1+1, T2-L2+1)
     lambda_frac: float       # lambda = lambda_frac * lambda_max
     dtype: str               # "f64" or "f32": the working precision of the solve
     tol_rel: float           # epsilon as a multiple of lambda (f32), or absolute (f64)
@@ -36,6 +38,13 @@ class Problem:
     @property
     def is_1d(self) -> bool:
         return self.X.ndim == 2
+
+    @property
+    def Z_true(self) -> np.ndarray:
+        """The generating activations as a dense array (built on each access)."""
+        Z = np.zeros(int(np.prod(self.zshape)))
+        Z[self.z_index] = self.z_value
+        return Z.reshape(self.zshape)
 
 
 def _rng(seed: int) -> np.random.Generator:
@@ -78,25 +87,35 @@ def _amplitudes(rng, kind: str, n: int) -> np.ndarray:
     raise ValueError(kind)
 
 
-def shifted_atom_sum(D: np.ndarray, Z: np.ndarray, T) -> np.ndarray:
-    """sum_k sum_w Z_k[w] (e_w * D_k): every non-zero activation adds a copy of
-    its atom at its position.  Works on the sparse support only."""
+def shifted_atom_sum(D: np.ndarray, index: np.ndarray, value: np.ndarray, zshape, T) -> np.ndarray:
+    """sum over the non-zero activations (flat `index` into zshape, `value`) of
+    a copy of the activation's atom at its position: X = Z*D of eq. model,
+    accumulated with one histogram per channel."""
     if D.ndim == 3:
-        X = shifted_atom_sum(D[:, :, None, :], Z[:, None, :], (1, int(T)))
+        X = shifted_atom_sum(D[:, :, None, :], index, value, (zshape[0], 1, zshape[1]), (1, int(T)))
         return X[:, 0, :]
     K, P, L1, L2 = D.shape
     T1, T2 = T
-    X = np.zeros((P, T1, T2))
+    H, W = zshape[1], zshape[2]
+    X = np.zeros((P, T1 * T2))
+    t1, t2 = np.meshgrid(np.arange(L1), np.arange(L2), indexing="ij")
+    tap = (t1 * T2 + t2).ravel()                       # flattened tap offsets
+    k_of = index // (H * W)
+    r = index - k_of * (H * W)
+    base_all = (r // W) * T2 + (r % W)                 # top-left corner in X
+    chunk = max(1, 4_000_000 // (L1 * L2))
     for k in range(K):
-        r1, r2 = np.nonzero(Z[k])
-        if r1.size == 0:
+        sel = k_of == k
+        if not sel.any():
             continue
-        v = Z[k, r1, r2]
-        for t1 in range(L1):
-            for t2 in range(L2):
-                # distinct (r1, r2) give distinct targets for a fixed offset
-                X[:, r1 + t1, r2 + t2] += D[k, :, t1, t2][:, None] * v[None, :]
-    return X
+        base, v = base_all[sel], value[sel]
+        Dk = D[k].reshape(P, L1 * L2)
+        for c in range(0, base.size, chunk):
+            idx = (base[c:c + chunk, None] + tap[None, :]).ravel()
+            for p in range(P):
+                w = (v[c:c + chunk, None] * Dk[p][None, :]).ravel()
+                X[p] += np.bincount(idx, weights=w, minlength=T1 * T2)
+    return X.reshape(P, T1, T2)
 
 
 def make_problem(name: str, seed: int, P: int, T, K: int, L, rho: float, amp: str,
@@ -114,12 +133,10 @@ def make_problem(name: str, seed: int, P: int, T, K: int, L, rho: float, amp: st
         zshape = (K, int(T[0]) - int(L[0]) + 1, int(T[1]) - int(L[1]) + 1)
     n = int(np.prod(zshape))
     idx = bernoulli_support(rng, n, rho)
-    Z = np.zeros(n)
-    Z[idx] = _amplitudes(rng, amp, idx.size)
-    Z = Z.reshape(zshape)
-    X = shifted_atom_sum(D, Z, T)
+    val = _amplitudes(rng, amp, idx.size)
+    X = shifted_atom_sum(D, idx, val, zshape, T)
     X = X + sigma * rng.standard_normal(X.shape)
-    return Problem(name, X, D, Z, lambda_frac, dtype, tol_rel, tol_abs,
+    return Problem(name, X, D, idx, val, zshape, lambda_frac, dtype, tol_rel, tol_abs,
                    meta=dict(seed=seed, rho=rho, amp=amp, sigma=sigma))
 
 

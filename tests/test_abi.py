@@ -51,6 +51,8 @@ int main(void) {
   printf("%zu %zu %zu\\n", sizeof(dcdl_shape), sizeof(dcdl_csc_opts), sizeof(dcdl_csc_info));
   printf("%zu %zu %zu %zu\\n", offsetof(dcdl_csc_opts, max_rounds), offsetof(dcdl_csc_opts, kkt_target),
          offsetof(dcdl_csc_info, converged), offsetof(dcdl_csc_info, n_passes));
+  printf("%zu %zu %zu %zu\\n", sizeof(dcdl_batch_opts), sizeof(dcdl_batch_info), sizeof(dcdl_csc_info),
+         offsetof(dcdl_csc_info, t_worker_apply_s));
   return 0;
 }
 """)
@@ -62,6 +64,9 @@ int main(void) {
     assert sizes == [ctypes.sizeof(dl.Shape), ctypes.sizeof(dl.CscOpts), ctypes.sizeof(dl.CscInfo)]
     assert offs == [dl.CscOpts.max_rounds.offset, dl.CscOpts.kkt_target.offset,
                     dl.CscInfo.converged.offset, dl.CscInfo.n_passes.offset]
+    more = [int(v) for v in lines[2].split()]
+    assert more == [ctypes.sizeof(dl.BatchOpts), ctypes.sizeof(dl.BatchInfo), ctypes.sizeof(dl.CscInfo),
+                    dl.CscInfo.t_worker_apply_s.offset]
 
 
 def test_argument_checks_before_device_access(lib):

@@ -1,0 +1,105 @@
+"""Batched solves (one persistent launch over many instances) against the
+FP64 oracle, and the same instance alone vs inside a batch."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09235_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_09235_amd as dl
+    dl.load()
+    return dl
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _batch(seed, n=6, lo=40, hi=90, K=4, L=(6, 6)):
+    rng = np.random.default_rng(seed)
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(seed)), K, 1, L)
+    pbs = []
+    for i in range(n):
+        h, w = (int(v) for v in rng.integers(lo, hi + 1, size=2))
+        pbs.append(synth.make_problem(f"b{i}", seed * 100 + i, P=1, T=(h, w), K=K, L=L, rho=0.01,
+                                      amp="uniform", sigma=0.1, D=D))
+    return D, pbs
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_batch_each_instance_matches_oracle(lib, dtype):
+    D, pbs = _batch(1)
+    lams = [0.1 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    rel = 1e-5 if dtype == torch.float32 else 1e-10
+    Xs = [dev(pb.X, dtype) for pb in pbs]
+    zs, infos, binfo = lib.dicodile_csc_batch(Xs, dev(D, dtype), lams, [rel * l for l in lams])
+    assert binfo["status"] == "OK" and binfo["n_converged"] == len(pbs), binfo
+    for pb, lam, z, info in zip(pbs, lams, zs, infos):
+        X = pb.X if dtype == torch.float64 else pb.X.astype(np.float32).astype(np.float64)
+        Dd = D if dtype == torch.float64 else D.astype(np.float32).astype(np.float64)
+        Zg = z.double().cpu().numpy()
+        Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
+        fo, fg = oracle.objective(X, Dd, Zo, lam), oracle.objective(X, Dd, Zg, lam)
+        assert (fg - fo) / fo <= 1e-6
+        assert oracle.kkt(X, Dd, Zg, lam) <= 1e-4
+        assert info["kkt"] == pytest.approx(oracle.kkt(X, Dd, Zg, lam), rel=1e-6, abs=1e-12)
+
+
+def test_batch_graph_and_direct_paths_agree_bitwise(lib):
+    D, pbs = _batch(2, n=4)
+    lams = [0.1 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    Xs = [dev(pb.X, torch.float32) for pb in pbs]
+    Dd = dev(D, torch.float32)
+    za, _, ba = lib.dicodile_csc_batch(Xs, Dd, lams, [1e-5 * l for l in lams], graph=True)
+    zb, _, bb = lib.dicodile_csc_batch(Xs, Dd, lams, [1e-5 * l for l in lams], graph=False)
+    assert ba["used_graph"] == 1 and bb["used_graph"] == 0
+    for a, b in zip(za, zb):
+        assert torch.equal(a, b)
+
+
+def test_instance_alone_and_in_batch(lib):
+    """The same instance alone and in a mix reaches the same minimiser
+    (objective within 1e-6 relative, KKT <= 1e-4 both ways)."""
+    D, pbs = _batch(3, n=5)
+    pb = pbs[2]
+    lam = 0.1 * oracle.lambda_max(pb.X, D)
+    Dd = dev(D, torch.float32)
+    z1, i1 = lib.dicodile_csc(dev(pb.X, torch.float32), Dd, lam, 1e-5 * lam, max_rounds=10**6, timeout_s=60)
+    lams = [0.1 * oracle.lambda_max(p.X, D) for p in pbs]
+    zs, infos, _ = lib.dicodile_csc_batch([dev(p.X, torch.float32) for p in pbs], Dd, lams,
+                                          [1e-5 * l for l in lams])
+    f1, f2 = i1["objective"], infos[2]["objective"]
+    assert abs(f1 - f2) / f1 <= 1e-6
+    assert i1["kkt"] <= 1e-4 and infos[2]["kkt"] <= 1e-4
+
+
+def test_batch_of_signals(lib):
+    rng = np.random.default_rng(4)
+    Dsig = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(4)), 3, 2, 24)
+    pbs = [synth.make_problem(f"s{i}", 400 + i, P=2, T=int(rng.integers(300, 1200)), K=3, L=24,
+                              rho=0.01, amp="exp", sigma=0.1, D=Dsig) for i in range(5)]
+    lams = [0.2 * oracle.lambda_max(pb.X, Dsig) for pb in pbs]
+    zs, infos, binfo = lib.dicodile_csc_batch([dev(pb.X, torch.float64) for pb in pbs],
+                                              dev(Dsig, torch.float64), lams, [1e-10 * l for l in lams])
+    assert binfo["n_converged"] == 5
+    for pb, lam, z in zip(pbs, lams, zs):
+        Zo, _ = oracle.lgcd(pb.X, Dsig, lam, 1e-11 * lam)
+        fo = oracle.objective(pb.X, Dsig, Zo, lam)
+        assert (oracle.objective(pb.X, Dsig, z.cpu().numpy(), lam) - fo) / fo <= 1e-6
+
+
+def test_batch_rejects_mismatched_atoms(lib):
+    D, pbs = _batch(5, n=2)
+    X0 = dev(pbs[0].X, torch.float32)
+    X1 = dev(np.zeros((2,) + pbs[1].X.shape[1:]), torch.float32)  # P differs
+    with pytest.raises(lib.DicodileError):
+        lib.dicodile_csc_batch([X0, X1], dev(D, torch.float32), [1.0, 1.0], [1e-5, 1e-5])
