@@ -55,7 +55,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="image_1024",
-                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images"])
+                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images", "serving"])
+    ap.add_argument("--requests", type=int, default=400, help="requests of the serving workload")
+    ap.add_argument("--pool", type=int, default=24, help="distinct request signals of the serving workload")
+    ap.add_argument("--rate", type=float, default=200.0, help="Poisson arrival rate of the serving workload")
+    ap.add_argument("--max-workers", type=int, default=0, help="server: workgroups per request at most")
+    ap.add_argument("--slice", type=int, default=0, help="server: rounds per launch")
     ap.add_argument("--batch-n", type=int, default=256, help="instances of the batch workload")
     ap.add_argument("--plain", type=int, default=-1,
                     help="batch workload: also time this many instances one solve per call "
@@ -179,8 +184,142 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _percentiles(v):
+    import numpy as np
+    a = np.sort(np.asarray(v, dtype=np.float64))
+    return {"p50_ms": float(np.percentile(a, 50) * 1e3), "p99_ms": float(np.percentile(a, 99) * 1e3),
+            "mean_ms": float(a.mean() * 1e3), "max_ms": float(a.max() * 1e3)}
+
+
+def run_serving(args):
+    """Serving pattern: Poisson arrivals of multichannel 1-D requests of
+    log-uniform length sharing one dictionary, served by continuous batching
+    (dicodile_server_*), beside the plain form: the same arrivals solved one
+    call at a time in arrival order.  Latency = arrival -> z ready."""
+    import threading
+    import numpy as np
+    import torch
+    import paper_1901_09235_amd as dl
+    from paper_1901_09235_amd import synth
+
+    t0 = time.perf_counter()
+    D_np = synth.serving_dictionary()
+    pool = [synth.serving_request(j, D_np) for j in range(args.pool)]
+    t_gen = time.perf_counter() - t0
+    print(f"# generated {len(pool)} request signals in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    D = torch.from_numpy(D_np).to("cuda", dtype=torch.float32).contiguous()
+    Xs = [torch.from_numpy(pb.X).to("cuda", dtype=torch.float32).contiguous() for pb in pool]
+    lams = [pb.lambda_frac * dl.dicodile_lambda_max(X, D) for pb, X in zip(pool, Xs)]
+    L = D.shape[2]
+    arrivals = synth.serving_arrivals(args.requests, rate_hz=args.rate)
+    which = [i % len(pool) for i in range(args.requests)]
+    zs = [torch.empty((D.shape[0], Xs[j].shape[1] - L + 1), dtype=torch.float32, device="cuda") for j in which]
+    torch.cuda.synchronize()
+    max_len = max(X.shape[1] for X in Xs)
+    sopts = dict(hbm_budget_bytes=32 << 30, max_len=max_len)
+    if args.max_workers:
+        sopts["max_workers"] = args.max_workers
+    if args.slice:
+        sopts["slice_rounds"] = args.slice
+
+    srv = dl.Server(D, **sopts)
+    try:
+        # warm-up: every pool signal once, all at once
+        tk = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
+        warm = [srv.wait(t) for t in tk]
+        for z, info in warm:
+            if info["status"] != "OK":
+                raise SystemExit(f"served warm-up request did not converge: {info}")
+        print("# warm-up done", file=sys.stderr, flush=True)
+        st0 = srv.stats()
+        results = [None] * args.requests
+        tickets = [None] * args.requests
+        sub_at = [0.0] * args.requests
+        ready = threading.Semaphore(0)
+
+        def collect():
+            for i in range(args.requests):
+                ready.acquire()
+                results[i] = srv.wait(tickets[i])[1]
+        th = threading.Thread(target=collect)
+        th.start()
+        start = time.monotonic() + 0.05
+        for i in range(args.requests):
+            delay = start + arrivals[i] - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            sub_at[i] = time.monotonic()
+            j = which[i]
+            tickets[i] = srv.submit(Xs[j], lams[j], 1e-5 * lams[j], z_out=zs[i])
+            ready.release()
+        th.join()
+        st1 = srv.stats()
+    finally:
+        srv.close()
+    lat = [(sub_at[i] - (start + arrivals[i])) + results[i]["t_total_s"] for i in range(args.requests)]
+    done_at = [sub_at[i] + results[i]["t_total_s"] for i in range(args.requests)]
+    span = max(done_at) - (start + arrivals[0])
+    bad = [r for r in results if r["status"] != "OK"]
+    if bad:
+        raise SystemExit(f"{len(bad)} served requests did not converge: {bad[0]}")
+    served_obj = {}
+    for i, r in enumerate(results):
+        served_obj.setdefault(which[i], r["objective"])
+    print(f"# served {args.requests} requests in {span:.2f} s", file=sys.stderr, flush=True)
+
+    # plain form: one dicodile_csc call per request, in arrival order
+    n_plain = args.requests if args.plain < 0 else min(args.plain, args.requests)
+    plain = None
+    gap = 0.0
+    if n_plain > 0:
+        for X, lam in zip(Xs[:2], lams[:2]):  # warm-up
+            dl.dicodile_csc(X, D, lam, 1e-5 * lam)
+        torch.cuda.synchronize()
+        plat, pdone = [], []
+        start = time.monotonic() + 0.05
+        for i in range(n_plain):
+            delay = start + arrivals[i] - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            j = which[i]
+            _, info = dl.dicodile_csc(Xs[j], D, lams[j], 1e-5 * lams[j], z_out=zs[i],
+                                      max_rounds=50_000_000, timeout_s=120)
+            if info["status"] != "OK":
+                raise SystemExit(f"plain solve did not converge: {info}")
+            now = time.monotonic()
+            plat.append(now - (start + arrivals[i]))
+            pdone.append(now)
+            gap = max(gap, abs(info["objective"] - served_obj[j]) / info["objective"])
+        pspan = pdone[-1] - (start + arrivals[0])
+        plain = dict(_percentiles(plat), requests=n_plain, requests_per_s=n_plain / pspan)
+        print(f"# plain form: {n_plain} requests in {pspan:.2f} s", file=sys.stderr, flush=True)
+
+    lens = [Xs[j].shape[1] for j in which]
+    out = {
+        "metric": "served requests/s with p50/p99 latency (arrival -> z at KKT tol), continuous batching vs plain",
+        "value": args.requests / span, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving_poisson{args.rate:g}_P32_K40_L128_T1e4-5e5",
+                   "requests": args.requests, "distinct_signals": len(pool), "offered_rate_hz": args.rate,
+                   "lambda": "0.2 lambda_max each", "tol": "1e-5 lambda each", "mean_T": float(np.mean(lens))},
+        "served": dict(_percentiles(lat), requests_per_s=args.requests / span),
+        "plain": plain,
+        "served_over_plain_throughput": (args.requests / span) / plain["requests_per_s"] if plain else None,
+        "max_objective_gap_served_vs_plain": gap if plain else None,
+        "max_kkt": max(r["kkt"] for r in results),
+        "queue_ms": _percentiles([r["t_init_s"] for r in results]),
+        "server": {k: st1[k] - st0.get(k, 0) if k in ("n_launches", "t_rounds_s", "t_busy_s", "n_done") else st1[k]
+                   for k in st1},
+        "generation_s": t_gen,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
+    if args.workload == "serving" and args.gpus == 1:
+        return run_serving(args)
     if args.workload == "batch_images" and args.gpus == 1:
         return run_batch(args)
     if args.gpus != 1:

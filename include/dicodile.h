@@ -45,6 +45,7 @@ extern "C" {
 typedef enum {
   DCDL_OK = 0,
   DCDL_NOT_CONVERGED = 1, /* stopped on max_updates / max_rounds / timeout; z holds the iterate */
+  DCDL_PENDING = 2,       /* dicodile_server_poll / _wait: the request has not finished yet */
   DCDL_EINVAL = -1,       /* bad shape, dtype, option or pointer */
   DCDL_ENOMEM = -2,       /* device memory or HBM budget exhausted */
   DCDL_EHIP = -3,         /* a HIP runtime call failed */
@@ -212,6 +213,85 @@ typedef struct {
 int dicodile_csc_batch(int32_t n, const dcdl_shape *shapes, const void *const *X, const void *D,
                        const dcdl_csc_opts *opts, void *const *z_out, dcdl_csc_info *infos,
                        const dcdl_batch_opts *bopts, dcdl_batch_info *binfo, void *stream);
+
+/* ------------------------------------------------------------------ serving
+ * A server solves a stream of eq. csc requests that share one dictionary,
+ * with continuous batching: requests are admitted while others run, as lanes
+ * and HBM free up, and every launch of the round kernel runs up to
+ * slice_rounds rounds of every admitted request that is ready (each on its
+ * own worker grid, with its own soft-lock rounds and stopping consensus,
+ * Alg. 3).  Between launches finished requests leave and new ones join; a
+ * request's stopping state carries over from one launch to the next.  Set-up
+ * (beta, move cache), the FP64 final check, drift-corrected polish passes and
+ * the output transpose of one request run on a second stream while the rounds
+ * of the others run.  The dictionary, its DtD table, beta, z and the cache of
+ * every admitted request stay resident in HBM.
+ *
+ * Threading: the server runs its own host thread; submit, poll and wait may
+ * be called from any thread.  A server holds device memory until destroyed. */
+typedef struct dcdl_server dcdl_server;
+
+/* Server options.  Zero-initialise for defaults. */
+typedef struct {
+  int64_t hbm_budget_bytes; /* device memory reserved for the working sets of admitted requests
+                               (beta, z, move cache: about 2 K s + 8 bytes per position, s the
+                               element size); 0 -> half of the free device memory */
+  int64_t max_len;          /* positions T (d = 1) or T1*T2 (d = 2) of the largest request; sizes
+                               the shared FP64 residual of the checks; 0 -> 2^20 */
+  int32_t max_workers;      /* workgroups of one request at most; 0 -> 128 */
+  int32_t slice_rounds;     /* rounds per launch between admissions; 0 -> 64 */
+  int32_t max_active;       /* admitted requests at most; 0 -> 256 */
+  int32_t threads;          /* threads per worker workgroup (64, 128, 256); 0 -> 256 */
+  int32_t tile[2];          /* sub-domain size; 0 -> 2 L_i (d = 1: tile[0] is the length) */
+  int32_t max_polish;       /* extra passes for requests failing the final check; 0 -> 2 */
+  int32_t reserved;
+} dcdl_server_opts;
+
+/* Counters of a server since its creation (host memory). */
+typedef struct {
+  int64_t n_submitted;
+  int64_t n_done;
+  int64_t n_launches;       /* launches of the round kernel */
+  int64_t peak_active;      /* most requests admitted at once */
+  int64_t peak_bytes;       /* most HBM budget in use at once */
+  int64_t peak_workers;     /* most workgroups in one launch */
+  double t_rounds_s;        /* summed duration of the round launches (HIP events) */
+  double t_busy_s;          /* host time with at least one admitted request */
+} dcdl_server_stats;
+
+/* Create a server on the current device.  dict_shape gives ndim, P, K and L of
+ * the dictionary (T is ignored); D: (K, P, L...) device, dtype; the server
+ * keeps its own copy.  *out receives the handle. */
+int dicodile_server_create(const dcdl_shape *dict_shape, dcdl_dtype dtype, const void *D,
+                           const dcdl_server_opts *opts, dcdl_server **out);
+
+/* Queue one request.  shape: ndim, P, K, L as the server's dictionary, any T.
+ * X: (P, T...) device, opts->dtype, complete (synchronised) before the call;
+ * z_out: (K, T-L+1 ...) device, opts->dtype.  Both must stay valid until the
+ * request has finished (poll or wait returned something other than
+ * DCDL_PENDING).  opts: as dicodile_csc (lambda, tol, positive, certify,
+ * dtype = the server's, kkt_target, max_rounds, timeout_s; warm_start is not
+ * supported).  *ticket identifies the request.  DCDL_ENOMEM if its working
+ * set exceeds the whole HBM budget. */
+int dicodile_server_submit(dcdl_server *sv, const dcdl_shape *shape, const void *X,
+                           const dcdl_csc_opts *opts, void *z_out, uint64_t *ticket);
+
+/* DCDL_PENDING while the request runs.  Otherwise its result as dicodile_csc
+ * returns it, with info (host, may be NULL) filled; info->t_total_s is the
+ * time from submit to z_out ready and info->t_init_s the time spent queued
+ * before admission.  A finished ticket is forgotten after this call. */
+int dicodile_server_poll(dcdl_server *sv, uint64_t ticket, dcdl_csc_info *info);
+
+/* As poll, blocking until the request finishes or timeout_s (> 0) passes
+ * (then DCDL_PENDING). */
+int dicodile_server_wait(dcdl_server *sv, uint64_t ticket, double timeout_s, dcdl_csc_info *info);
+
+/* Counters since creation. */
+int dicodile_server_stats(dcdl_server *sv, dcdl_server_stats *stats);
+
+/* Finish every queued and running request, stop the server thread and free
+ * the server's device memory.  Unretrieved results are dropped. */
+int dicodile_server_destroy(dcdl_server *sv);
 
 /* Streaming copy dst = src of `bytes` bytes (16-byte aligned, a multiple of
  * 16), `repeats` times; *seconds (host, may be NULL) receives the average time

@@ -19,13 +19,13 @@ import os
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
            "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
            "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch", "dicodile_release",
-           "STATUS"]
+           "Server", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "libdicodile_mi355x.so")
 _lib = None
 
-STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
+STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
           -4: "EDIVERGED", -5: "ETIMEOUT", -6: "ENODEV"}
 F32, F64 = 0, 1
 
@@ -69,6 +69,21 @@ class CscInfo(ctypes.Structure):
                 ("t_worker_apply_s", ctypes.c_double)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_len", ctypes.c_int64),
+                ("max_workers", ctypes.c_int32), ("slice_rounds", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("tile", ctypes.c_int32 * 2), ("max_polish", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("n_submitted", ctypes.c_int64), ("n_done", ctypes.c_int64),
+                ("n_launches", ctypes.c_int64), ("peak_active", ctypes.c_int64),
+                ("peak_bytes", ctypes.c_int64), ("peak_workers", ctypes.c_int64),
+                ("t_rounds_s", ctypes.c_double), ("t_busy_s", ctypes.c_double)]
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -97,8 +112,17 @@ def load():
     lib.dicodile_csc_batch.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, vp]
+    lib.dicodile_server_create.argtypes = [sp, i32, vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    lib.dicodile_server_submit.argtypes = [vp, sp, vp, ctypes.POINTER(CscOpts), vp,
+                                           ctypes.POINTER(ctypes.c_uint64)]
+    lib.dicodile_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(CscInfo)]
+    lib.dicodile_server_wait.argtypes = [vp, ctypes.c_uint64, dbl, ctypes.POINTER(CscInfo)]
+    lib.dicodile_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    lib.dicodile_server_destroy.argtypes = [vp]
     for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch"):
+              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch",
+              "dicodile_server_create", "dicodile_server_submit", "dicodile_server_poll",
+              "dicodile_server_wait", "dicodile_server_stats", "dicodile_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -385,3 +409,114 @@ def dicodile_csc_batch(Xs, D, lams, tols, z_outs=None, stream=None, graph=True, 
     bd = {f: getattr(bi, f) for f, _ in BatchInfo._fields_ if f != "reserved"}
     bd["status"] = STATUS.get(rc, rc)
     return outs, il, bd
+
+
+_live_servers = set()
+
+
+def _close_live_servers():
+    for srv in list(_live_servers):
+        srv.close()
+
+
+class Server:
+    """Continuous-batching CSC server over one dictionary (dicodile_server_*).
+
+    ``submit`` queues a request and returns a ticket; ``wait``/``poll`` return
+    (z, info dict) once it has finished.  X and z stay referenced here until
+    then.  Use as a context manager or call ``close``; servers still open at
+    interpreter exit are closed then."""
+
+    def __init__(self, D, hbm_budget_bytes=0, max_len=0, max_workers=0, slice_rounds=0,
+                 max_active=0, threads=0, tile=None, max_polish=0):
+        lib = load()
+        _device_tensor(D, "D")
+        self.dtype_code = _dtype_code(D)
+        self.D = D
+        s = Shape()
+        if D.dim() == 3:
+            s.ndim, s.P, s.K, s.L[0] = 1, D.shape[1], D.shape[0], D.shape[2]
+            s.T[0] = D.shape[2]
+        elif D.dim() == 4:
+            s.ndim, s.P, s.K = 2, D.shape[1], D.shape[0]
+            s.L[0], s.L[1] = D.shape[2], D.shape[3]
+            s.T[0], s.T[1] = D.shape[2], D.shape[3]
+        else:
+            raise DicodileError(-1, f"unsupported dictionary shape {tuple(D.shape)}")
+        o = ServerOpts()
+        o.hbm_budget_bytes, o.max_len = int(hbm_budget_bytes), int(max_len)
+        o.max_workers, o.slice_rounds, o.max_active = int(max_workers), int(slice_rounds), int(max_active)
+        o.threads, o.max_polish = int(threads), int(max_polish)
+        if tile is not None:
+            t = (tile, 0) if isinstance(tile, int) else tuple(tile)
+            o.tile[0], o.tile[1] = int(t[0]), int(t[1])
+        h = ctypes.c_void_p()
+        _check(lib.dicodile_server_create(ctypes.byref(s), self.dtype_code, ctypes.c_void_p(D.data_ptr()),
+                                          ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+        _live_servers.add(self)
+
+    def submit(self, X, lam: float, tol: float, z_out=None, **opts) -> int:
+        """Queue one request; X must be complete on the device (synchronised)."""
+        torch = _torch()
+        lib = load()
+        _device_tensor(X, "X")
+        if X.dtype != self.D.dtype:
+            raise DicodileError(-1, "X must share the dictionary's dtype")
+        s = _shape(X, self.D)
+        if z_out is None:
+            z_out = torch.empty(_zshape(s), dtype=X.dtype, device=X.device)
+        _device_tensor(z_out, "z_out")
+        if tuple(z_out.shape) != _zshape(s) or z_out.dtype != X.dtype:
+            raise DicodileError(-1, f"z_out must be {_zshape(s)} {X.dtype}")
+        o = make_opts(lam, tol, self.dtype_code, **opts)
+        t = ctypes.c_uint64()
+        _check(lib.dicodile_server_submit(self._h, ctypes.byref(s), ctypes.c_void_p(X.data_ptr()),
+                                          ctypes.byref(o), ctypes.c_void_p(z_out.data_ptr()),
+                                          ctypes.byref(t)))
+        self._keep[t.value] = (X, z_out)
+        return t.value
+
+    def _finish(self, ticket, rc, info):
+        if rc == 2:
+            return None
+        X, z = self._keep.pop(ticket, (None, None))
+        _check(rc, allow_not_converged=True)
+        return z, info_dict(info, rc)
+
+    def poll(self, ticket: int):
+        """(z, info) if finished, else None."""
+        info = CscInfo()
+        rc = load().dicodile_server_poll(self._h, ctypes.c_uint64(ticket), ctypes.byref(info))
+        return self._finish(ticket, rc, info)
+
+    def wait(self, ticket: int, timeout_s: float = 0.0):
+        """Block until the request finishes: (z, info); None on timeout."""
+        info = CscInfo()
+        rc = load().dicodile_server_wait(self._h, ctypes.c_uint64(ticket), float(timeout_s), ctypes.byref(info))
+        return self._finish(ticket, rc, info)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(load().dicodile_server_stats(self._h, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            h, self._h = self._h, None
+            _live_servers.discard(self)
+            rc = load().dicodile_server_destroy(h)
+            self._keep.clear()
+            _check(rc)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+import atexit as _atexit  # noqa: E402
+
+_atexit.register(_close_live_servers)

@@ -3,7 +3,10 @@
 // include/dicodile.h.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
+#include <condition_variable>
+#include <deque>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -11,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dicodile.h"
@@ -167,9 +171,13 @@ int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *d
 template <class Rin, class Racc, class Rz, int MODE>
 int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, const CorrOut &o) {
   constexpr int KC = sizeof(Racc) == 8 ? 8 : 16;
-  dim3 grid(blocks_for(g.W, 32), blocks_for(g.H, 8));
   const size_t lds = sizeof(Racc) * (size_t)g.L2 * KC;
-  hipLaunchKernelGGL((corr_kernel<Rin, Racc, Rz, MODE, KC>), grid, dim3(256), lds, stream, g, X, D, o);
+  if (g.H == 1)
+    hipLaunchKernelGGL((corr_kernel<Rin, Racc, Rz, MODE, KC, 1>), dim3(blocks_for(g.W, 256)), dim3(256), lds, stream,
+                       g, X, D, o);
+  else
+    hipLaunchKernelGGL((corr_kernel<Rin, Racc, Rz, MODE, KC, 8>), dim3(blocks_for(g.W, 32), blocks_for(g.H, 8)),
+                       dim3(256), lds, stream, g, X, D, o);
   HIPCK(hipGetLastError());
   return DCDL_OK;
 }
@@ -812,3 +820,4 @@ extern "C" int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, co
   return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
 }
 #include "batch.inc"
+#include "serve.inc"

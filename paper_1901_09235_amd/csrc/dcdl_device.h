@@ -93,6 +93,10 @@ template <class R> struct Inst {
   int *prog;
   Ctl *ctl;
   int *ring;  // done[kRing] then active[kRing]
+  // optional, 2 per worker: visits so far and the quiet count, loaded at the
+  // start of a launch and stored at its end, so that a solve split over
+  // several launches (each capped by max_rounds) keeps its stopping state
+  long long *wstate;
 };
 
 // ----------------------------------------------------------------- arithmetic
@@ -394,31 +398,37 @@ __device__ __forceinline__ void patch_region(const Inst<R> &I, const PatchCtx<R,
 // >= tol and no patch touched S_w since.  When every worker reports quiet at
 // the end of the same round, every coordinate's move is below tol and no
 // further update can happen: all workers exit.
-template <class R, int NT>
-__global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ insts,
-                                                   const int *__restrict__ wg_inst,
-                                                   long long timeout_ticks) {
-  constexpr int LBUF = 4096;
-  constexpr int NWAVE = NT / 64;
-  constexpr int VE = Vec<R>::N;
-  __shared__ R sh_ps[LBUF];
-  __shared__ uint16_t sh_pk[LBUF];
-  __shared__ R sh_inv_n[1024];
-  __shared__ R sh_rs[NWAVE];
-  __shared__ int sh_ri[NWAVE];
-  __shared__ int sh_exit;
-  __shared__ int sh_wait;
-  __shared__ int sh_cok;
-  __shared__ int sh_k0;
-  __shared__ R sh_d;
-  __shared__ unsigned long long sh_tag[9];
-  __shared__ R sh_delta[9];
-  __shared__ int sh_nbr[9];
+template <class R, int NT> struct RoundSmem {
+  static constexpr int LBUF = 4096;
+  R ps[LBUF];
+  uint16_t pk[LBUF];
+  R inv_n[1024];
+  R rs[NT / 64];
+  int ri[NT / 64];
+  int exit_f, wait_f, cok, k0;
+  R d;
+  unsigned long long tag[9];
+  R delta[9];
+  int nbr[9];
+};
 
-  const int ii = wg_inst[blockIdx.x];
-  const Inst<R> I = insts[ii];
+// Runs worker w of instance I until its instance converges or stops.  Every
+// thread of the workgroup calls it.
+template <class R, int NT>
+__device__ void run_worker(const Inst<R> &I, const int w, const long long timeout_ticks, RoundSmem<R, NT> &sm) {
+  constexpr int VE = Vec<R>::N;
+  R *const sh_inv_n = sm.inv_n;
+  R *const sh_rs = sm.rs;
+  int *const sh_ri = sm.ri;
+  int &sh_exit = sm.exit_f;
+  int &sh_wait = sm.wait_f;
+  int &sh_cok = sm.cok;
+  int &sh_k0 = sm.k0;
+  R &sh_d = sm.d;
+  unsigned long long *const sh_tag = sm.tag;
+  R *const sh_delta = sm.delta;
+  int *const sh_nbr = sm.nbr;
   const int tid = threadIdx.x;
-  const int w = blockIdx.x - I.wg_base;
   const int nW = I.W1 * I.W2;
   const int wi = w / I.W2, wj = w - wi * I.W2;
   const int K = I.K, H = I.H, W = I.W;
@@ -434,8 +444,8 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
   const int in_lo2 = wj > 0 ? a2 + 2 * (I.L2 - 1) : a2, in_hi2 = wj < I.W2 - 1 ? b2 - 2 * (I.L2 - 1) : b2;
 
   PatchCtx<R, NT> P;
-  P.sh_ps = sh_ps;
-  P.sh_pk = sh_pk;
+  P.sh_ps = sm.ps;
+  P.sh_pk = sm.pk;
   P.sh_inv_n = sh_inv_n;
   P.G = I.KS / VE;
   P.spl = NT / P.G;
@@ -443,6 +453,7 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
   P.pl0 = tid / P.G;
   P.q0 = tid - P.pl0 * P.G;
 
+  __syncthreads();
   for (int k = tid; k < I.KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
   if (tid == 0) {
     int nn = 0;
@@ -464,8 +475,8 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
 
   unsigned long long my_upd = 0, my_cand = 0, my_lock = 0, my_visit = 0, my_chk = 0, my_patch = 0;
   unsigned long long tk_wait = 0, tk_sel = 0, tk_col = 0, tk_app = 0, tk_mark = 0;
-  long long cursor = 0;  // visits so far
-  int quiet = 0;         // consecutive visits with no move >= tol and no patch of S_w
+  long long cursor = I.wstate ? I.wstate[2 * w] : 0;         // visits so far
+  int quiet = I.wstate ? (int)I.wstate[2 * w + 1] : 0;  // consecutive visits with no move >= tol and no patch of S_w
   const unsigned long long t_launch = __builtin_amdgcn_s_memrealtime();
   int r = 0;
   int exit_status = 0;
@@ -473,8 +484,9 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
     // ---- exit conditions
     if (tid == 0) {
       int f = ld_shared_i32(&I.ctl->converged) | ld_shared_i32(&I.ctl->stop);
+      // every worker runs exactly max_rounds rounds: all moves of the last
+      // round are then applied everywhere and the launch can be resumed
       if (!f && I.max_rounds > 0 && r >= I.max_rounds) {
-        st_shared_i32(&I.ctl->stop, 1);
         atomicCAS(&I.ctl->status, 0, 1);
         f = 1;
       }
@@ -729,8 +741,22 @@ __global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ in
     atomicAdd(&I.ctl->tk_apply, tk_app);
     atomicMax(&I.ctl->max_round, r);
     atomicMax(&I.ctl->sweeps_done, (int)(cursor / Mw));
+    if (I.wstate) {
+      I.wstate[2 * w] = cursor;
+      I.wstate[2 * w + 1] = quiet;
+    }
     st_shared_i32(I.prog + w, 0x7fffffff);
   }
+}
+
+template <class R, int NT>
+__global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ insts,
+                                                   const int *__restrict__ wg_inst,
+                                                   long long timeout_ticks) {
+  __shared__ RoundSmem<R, NT> sm;
+  const int ii = wg_inst[blockIdx.x];
+  const Inst<R> I = insts[ii];
+  run_worker<R, NT>(I, blockIdx.x - I.wg_base, timeout_ticks, sm);
 }
 
 }  // namespace dcdl

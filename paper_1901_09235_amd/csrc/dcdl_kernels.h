@@ -89,7 +89,8 @@ __global__ __launch_bounds__(256) void dtd_kernel(Geom g, const R *__restrict__ 
 // ------------------------------------------------------------- correlation
 // G[pos][k] = sum_p sum_t D[k,p,t] X[p, pos + t] on the valid domain, computed
 // directly: one thread per output position, KC atoms at a time, the slice
-// D[k-chunk, p, t1, :] staged in LDS.  Tile: 8 rows x 32 columns of positions.
+// D[k-chunk, p, t1, :] staged in LDS.  Tile: TH rows x 256/TH columns of
+// positions (TH = 1 for signals, 8 for images).
 enum CorrMode { CORR_BETA = 0, CORR_KKT = 1, CORR_ABSMAX = 2 };
 
 struct CorrOut {
@@ -101,10 +102,10 @@ struct CorrOut {
   double *result;      // CORR_KKT: max violation; CORR_ABSMAX: max |G| (one-sided if positive)
 };
 
-template <class Rin, class Racc, class Rz, int MODE, int KC>
+template <class Rin, class Racc, class Rz, int MODE, int KC, int TH>
 __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict__ X, const Rin *__restrict__ D,
                                                    CorrOut o) {
-  constexpr int TH = 8, TW = 32;
+  constexpr int TW = 256 / TH;
   extern __shared__ unsigned char smem_raw[];
   Racc *ds = reinterpret_cast<Racc *>(smem_raw);  // [L2][KC]
   __shared__ double sh_red[4];

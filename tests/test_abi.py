@@ -53,6 +53,8 @@ int main(void) {
          offsetof(dcdl_csc_info, converged), offsetof(dcdl_csc_info, n_passes));
   printf("%zu %zu %zu %zu\\n", sizeof(dcdl_batch_opts), sizeof(dcdl_batch_info), sizeof(dcdl_csc_info),
          offsetof(dcdl_csc_info, t_worker_apply_s));
+  printf("%zu %zu %zu %zu\\n", sizeof(dcdl_server_opts), sizeof(dcdl_server_stats),
+         offsetof(dcdl_server_opts, tile), offsetof(dcdl_server_stats, t_busy_s));
   return 0;
 }
 """)
@@ -67,6 +69,9 @@ int main(void) {
     more = [int(v) for v in lines[2].split()]
     assert more == [ctypes.sizeof(dl.BatchOpts), ctypes.sizeof(dl.BatchInfo), ctypes.sizeof(dl.CscInfo),
                     dl.CscInfo.t_worker_apply_s.offset]
+    srv = [int(v) for v in lines[3].split()]
+    assert srv == [ctypes.sizeof(dl.ServerOpts), ctypes.sizeof(dl.ServerStats), dl.ServerOpts.tile.offset,
+                   dl.ServerStats.t_busy_s.offset]
 
 
 def test_argument_checks_before_device_access(lib):
@@ -86,6 +91,13 @@ def test_argument_checks_before_device_access(lib):
     rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(o),
                           ctypes.c_void_p(1), ctypes.byref(info), None)
     assert rc == -1 and b"lambda" in lib.dicodile_last_error()
+    # server calls: NULL handles and arguments are rejected before any device access
+    assert lib.dicodile_server_create(None, 0, None, None, None) == -1
+    assert lib.dicodile_server_submit(None, None, None, None, None, None) == -1
+    assert lib.dicodile_server_poll(None, 1, None) == -1
+    assert lib.dicodile_server_wait(None, 1, 0.0, None) == -1
+    assert lib.dicodile_server_stats(None, None) == -1
+    assert lib.dicodile_server_destroy(None) == 0
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -1,0 +1,161 @@
+"""Serving (continuous batching): every request served alone and in a mix
+against the FP64 oracle, time slicing across launches, admission by the HBM
+budget, and the error paths of the server calls."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09235_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_09235_amd as dl
+    dl.load()
+    return dl
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def _requests(seed, lengths, P=4, K=8, L=32):
+    """Multichannel 1-D requests of the given lengths over one dictionary."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(seed)), K, P, L)
+    pbs = [synth.make_problem(f"r{i}", seed * 100 + i, P=P, T=T, K=K, L=L, rho=0.004, amp="exp",
+                              sigma=0.1, D=D) for i, T in enumerate(lengths)]
+    return D, pbs
+
+
+def _check_against_oracle(pb, D, lam, z, info, dtype):
+    X = pb.X if dtype == torch.float64 else pb.X.astype(np.float32).astype(np.float64)
+    Dd = D if dtype == torch.float64 else D.astype(np.float32).astype(np.float64)
+    Zg = z.double().cpu().numpy()
+    Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
+    fo, fg = oracle.objective(X, Dd, Zo, lam), oracle.objective(X, Dd, Zg, lam)
+    assert (fg - fo) / fo <= 1e-6, (pb.name, fg, fo)
+    kk = oracle.kkt(X, Dd, Zg, lam)
+    assert kk <= 1e-4, (pb.name, kk)
+    assert info["kkt"] == pytest.approx(kk, rel=1e-6, abs=1e-12)
+    assert info["objective"] == pytest.approx(fg, rel=1e-9)
+    return fg
+
+
+@pytest.mark.parametrize("dtype", [torch.float32, torch.float64])
+def test_each_request_alone_and_in_the_mix(lib, dtype):
+    """Requests of different lengths, each served alone and then all at once
+    (sharing launches): every result meets the oracle's objective (gap
+    <= 1e-6) and KKT (<= 1e-4) both ways, and the two results agree."""
+    lengths = [40, 600, 2500, 5000, 1300, 3600, 900]
+    D, pbs = _requests(11, lengths)
+    Dd = dev(D, dtype)
+    lams = [0.2 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    rel = 1e-5 if dtype == torch.float32 else 1e-10
+    Xs = [dev(pb.X, dtype) for pb in pbs]
+    torch.cuda.synchronize()
+    alone = []
+    with lib.Server(Dd, max_workers=16, slice_rounds=32, max_len=8192) as srv:
+        for X, lam in zip(Xs, lams):
+            t = srv.submit(X, lam, rel * lam)
+            z, info = srv.wait(t)
+            assert info["status"] == "OK", info
+            alone.append((z.clone(), info))
+        tickets = [srv.submit(X, lam, rel * lam) for X, lam in zip(Xs, lams)]
+        mixed = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["n_done"] == 2 * len(pbs) and st["peak_active"] >= 2
+    for pb, lam, (za, ia), (zm, im) in zip(pbs, lams, alone, mixed):
+        assert im["status"] == "OK", im
+        fa = _check_against_oracle(pb, D, lam, za, ia, dtype)
+        fm = _check_against_oracle(pb, D, lam, zm, im, dtype)
+        assert abs(fa - fm) / fa <= 1e-6
+
+
+def test_long_request_spans_many_slices(lib):
+    """A request needing far more rounds than one launch's slice resumes its
+    stopping state across launches and converges to the oracle's minimiser,
+    while short requests submitted after it finish first."""
+    D, pbs = _requests(12, [6000, 300, 500])
+    Dd = dev(D, torch.float32)
+    lams = [0.1 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    Xs = [dev(pb.X, torch.float32) for pb in pbs]
+    torch.cuda.synchronize()
+    with lib.Server(Dd, max_workers=4, slice_rounds=8, max_len=8192) as srv:
+        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["n_launches"] > 10
+    long_info = res[0][1]
+    assert long_info["n_rounds"] > 8 and long_info["status"] == "OK"
+    assert res[1][1]["t_total_s"] < long_info["t_total_s"]
+    for pb, lam, (z, info) in zip(pbs, lams, res):
+        _check_against_oracle(pb, D, lam, z, info, torch.float32)
+
+
+def test_image_requests(lib):
+    """2-D requests through the server match the oracle."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(13)), 4, 1, (6, 6))
+    pbs = [synth.make_problem(f"i{i}", 1300 + i, P=1, T=hw, K=4, L=(6, 6), rho=0.01, amp="uniform",
+                              sigma=0.1, D=D) for i, hw in enumerate([(40, 70), (64, 48), (30, 30)])]
+    Dd = dev(D, torch.float32)
+    lams = [0.1 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    torch.cuda.synchronize()
+    with lib.Server(Dd, max_workers=9, slice_rounds=16, max_len=4096) as srv:
+        Xs = [dev(pb.X, torch.float32) for pb in pbs]
+        torch.cuda.synchronize()
+        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t) for t in tickets]
+    for pb, lam, (z, info) in zip(pbs, lams, res):
+        assert info["status"] == "OK"
+        _check_against_oracle(pb, D, lam, z, info, torch.float32)
+
+
+def test_admission_waits_for_memory(lib):
+    """With a budget that holds one request's working set at a time, requests
+    are admitted one after another and still all finish correctly."""
+    D, pbs = _requests(14, [3000, 3000, 3000])
+    Dd = dev(D, torch.float32)
+    lams = [0.2 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    Xs = [dev(pb.X, torch.float32) for pb in pbs]
+    torch.cuda.synchronize()
+    # beta + z (2 * 8 * 4 B) + score (4 B) + meta (4 B) per position, rounded up
+    one = 2 * 8 * 4 * 2969 + 8 * 2969 + 4 * 256
+    with lib.Server(Dd, hbm_budget_bytes=one + one // 2, max_len=4096) as srv:
+        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t) for t in tickets]
+        st = srv.stats()
+    assert st["peak_active"] == 1
+    for pb, lam, (z, info) in zip(pbs, lams, res):
+        _check_against_oracle(pb, D, lam, z, info, torch.float32)
+
+
+def test_server_errors(lib):
+    D, pbs = _requests(15, [500])
+    Dd = dev(D, torch.float32)
+    X = dev(pbs[0].X, torch.float32)
+    torch.cuda.synchronize()
+    with lib.Server(Dd, hbm_budget_bytes=1 << 16, max_len=1024) as srv:
+        with pytest.raises(lib.DicodileError):        # over the whole budget
+            srv.submit(dev(np.zeros((4, 1000)), torch.float32), 1.0, 1e-5)
+        with pytest.raises(lib.DicodileError):        # longer than max_len
+            srv.submit(dev(np.zeros((4, 2000)), torch.float32), 1.0, 1e-5)
+        with pytest.raises(lib.DicodileError):        # wrong channel count
+            srv.submit(dev(np.zeros((3, 500)), torch.float32), 1.0, 1e-5)
+        with pytest.raises(lib.DicodileError):        # wrong dtype
+            srv.submit(dev(pbs[0].X, torch.float64), 1.0, 1e-5)
+        with pytest.raises(lib.DicodileError):        # lambda <= 0
+            srv.submit(X, 0.0, 1e-5)
+        with pytest.raises(lib.DicodileError):        # unknown ticket
+            srv.poll(12345)
+        lam = 0.2 * oracle.lambda_max(pbs[0].X, D)
+        t = srv.submit(X, lam, 1e-5 * lam)
+        z, info = srv.wait(t)
+        assert info["status"] == "OK"
+        with pytest.raises(lib.DicodileError):        # a finished ticket is forgotten
+            srv.poll(t)
