@@ -56,6 +56,19 @@ typedef enum {
 
 typedef enum { DCDL_F32 = 0, DCDL_F64 = 1 } dcdl_dtype;
 
+/* Precision of the dense correlation corr(R, D) (beta initialisation,
+ * dicodile_corr).  The matrix-core paths need (P * L1 * L2 small enough that a
+ * staged window fits 64 KB of LDS: P up to 8 x L2 up to ~700 for signals);
+ * otherwise DIRECT is used. */
+typedef enum {
+  DCDL_CORR_AUTO = 0,    /* FP32 data: BF16X3; FP64 data: F64 */
+  DCDL_CORR_F64 = 1,     /* v_mfma_f64_16x16x4: FP64 products and sums */
+  DCDL_CORR_BF16 = 2,    /* v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 sums (FP32 data only) */
+  DCDL_CORR_BF16X3 = 3,  /* the same on hi/lo BF16 splits (hi*hi + hi*lo + lo*hi), about FP32
+                            accuracy (FP32 data only) */
+  DCDL_CORR_DIRECT = 4   /* vector FMA in the data's precision, no matrix cores */
+} dcdl_corr_prec;
+
 /* Problem shape.  ndim = 1: T[0] = T, L[0] = L (T[1], L[1] ignored).
  * ndim = 2: T = (T1, T2), L = (L1, L2).  Requires 1 <= L_i <= T_i, P >= 1,
  * 1 <= K <= 1024. */
@@ -87,6 +100,9 @@ typedef struct {
                              (drift correction, FP64 contraction); 0 -> only at the end */
   int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
   int32_t inner;          /* sub-domain visits per worker per round; 0 -> 1 */
+  int32_t beta_prec;      /* dcdl_corr_prec of the contraction that initialises beta from X
+                             (0 -> FP32: BF16X3 matrix cores; FP64: FP64 matrix cores).  The
+                             drift correction and the final check are FP64 whatever this is */
   int64_t max_rounds;     /* cap on worker rounds (0 -> unlimited) */
   double div_guard;       /* stop with DCDL_EDIVERGED if |Z| exceeds this (0 -> off) */
   double timeout_s;       /* wall-clock cap for the whole call (0 -> none) */
@@ -155,6 +171,15 @@ int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X
  * beta and Z are kept in opts->dtype; the final objective/KKT are FP64. */
 int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D,
                  const dcdl_csc_opts *opts, void *z_out, dcdl_csc_info *info, void *stream);
+
+/* Dense correlation G = corr(X, D) (Sec. 2: the paper's X * D~_k; beta at
+ * Z = 0, and the gradient -G of the data term):
+ *   G[k][w] = sum_p sum_t D_{k,p}[t] X_p[w + t],  w on the valid domain.
+ * X: (P, T...) device, dtype.  D: (K, P, L...) device, dtype.
+ * out: (K, T-L+1 ...) device, dtype.  prec: dcdl_corr_prec (the BF16 paths
+ * need dtype F32).  For measuring the matrix-core contraction and its error. */
+int dicodile_corr(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D, void *out,
+                  int32_t prec, void *stream);
 
 /* FP64 objective F(Z) = 1/2||X - Z*D||^2 + lambda ||Z||_1 and strict KKT
  * violation / lambda (with g = corr(X - Z*D, D): max(|g| - lambda, 0) on

@@ -18,7 +18,7 @@ import os
 
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
            "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-           "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch", "dicodile_release",
+           "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch", "dicodile_release",
            "Server", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +28,7 @@ _lib = None
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
           -4: "EDIVERGED", -5: "ETIMEOUT", -6: "ENODEV"}
 F32, F64 = 0, 1
+CORR_PREC = {"auto": 0, "f64": 1, "bf16": 2, "bf16x3": 3, "direct": 4}
 
 
 class DicodileError(RuntimeError):
@@ -48,7 +49,7 @@ class CscOpts(ctypes.Structure):
                 ("threads", ctypes.c_int32), ("tile", ctypes.c_int32 * 2),
                 ("grid", ctypes.c_int32 * 2), ("warm_start", ctypes.c_int32),
                 ("refresh_every", ctypes.c_int32), ("max_polish", ctypes.c_int32),
-                ("inner", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
+                ("inner", ctypes.c_int32), ("beta_prec", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
                 ("kkt_target", ctypes.c_double)]
 
@@ -108,6 +109,7 @@ def load():
     lib.dicodile_objective_kkt.argtypes = [sp, i32, vp, vp, vp, dbl, i32, ctypes.POINTER(dbl),
                                            ctypes.POINTER(dbl), vp]
     lib.dicodile_dict_stats.argtypes = [sp, i32, vp, vp, vp, vp, vp]
+    lib.dicodile_corr.argtypes = [sp, i32, vp, vp, vp, i32, vp]
     lib.dicodile_copy_probe.argtypes = [vp, vp, ctypes.c_size_t, i32, ctypes.POINTER(dbl), vp]
     lib.dicodile_csc_batch.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -119,8 +121,8 @@ def load():
     lib.dicodile_server_wait.argtypes = [vp, ctypes.c_uint64, dbl, ctypes.POINTER(CscInfo)]
     lib.dicodile_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.dicodile_server_destroy.argtypes = [vp]
-    for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_csc_batch",
+    for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt", "dicodile_corr",
+              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch",
               "dicodile_server_create", "dicodile_server_submit", "dicodile_server_poll",
               "dicodile_server_wait", "dicodile_server_stats", "dicodile_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -226,7 +228,8 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
-              div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0) -> CscOpts:
+              div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0,
+              beta_prec=0) -> CscOpts:
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -241,6 +244,7 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
     o.max_rounds, o.div_guard, o.timeout_s = int(max_rounds), float(div_guard), float(timeout_s)
     o.kkt_target = float(kkt_target)
     o.inner = int(inner)
+    o.beta_prec = CORR_PREC[beta_prec] if isinstance(beta_prec, str) else int(beta_prec)
     return o
 
 
@@ -281,6 +285,28 @@ def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
                           ctypes.c_void_p(z_out.data_ptr()), ctypes.byref(info), _stream(stream))
     _check(rc, allow_not_converged=True)
     return z_out, info_dict(info, rc)
+
+
+def dicodile_corr(X, D, prec="auto", out=None, stream=None):
+    """G = corr(X, D) on the valid domain, shape (K, T-L+1 ...), in X's dtype.
+    prec: "auto", "f64", "bf16", "bf16x3" or "direct" (dcdl_corr_prec)."""
+    torch = _torch()
+    lib = load()
+    _device_tensor(X, "X")
+    _device_tensor(D, "D")
+    s = _shape(X, D)
+    if D.dtype != X.dtype:
+        raise DicodileError(-1, "X and D must share a dtype")
+    if out is None:
+        out = torch.empty(_zshape(s), dtype=X.dtype, device=X.device)
+    _device_tensor(out, "out")
+    if tuple(out.shape) != _zshape(s) or out.dtype != X.dtype:
+        raise DicodileError(-1, f"out must be {_zshape(s)} {X.dtype}")
+    code = CORR_PREC[prec] if isinstance(prec, str) else int(prec)
+    _check(lib.dicodile_corr(ctypes.byref(s), _dtype_code(X), ctypes.c_void_p(X.data_ptr()),
+                             ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(out.data_ptr()), code,
+                             _stream(stream)))
+    return out
 
 
 def dicodile_objective_kkt(X, D, z, lam: float, positive: bool = False, stream=None):

@@ -14,12 +14,14 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <thread>
 #include <vector>
 
 #include "../../include/dicodile.h"
 #include "dcdl_device.h"
 #include "dcdl_kernels.h"
+#include "dcdl_mfma.h"
 
 using namespace dcdl;
 
@@ -182,6 +184,82 @@ int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, cons
   return DCDL_OK;
 }
 
+#include "mfma_host.inc"
+
+int mf_of(int prec) { return prec == DCDL_CORR_F64 ? MF_F64 : (prec == DCDL_CORR_BF16 ? MF_BF16 : MF_BF16X3); }
+
+// The contraction actually used for a requested dcdl_corr_prec on data of
+// type R: AUTO picks BF16X3 for FP32 and F64 for FP64; the matrix-core
+// paths fall back to DIRECT when the staged windows would not fit.  -1 for a
+// BF16 request on FP64 data.
+int resolve_prec(int want, bool f32, const Geom &g) {
+  int p = want == DCDL_CORR_AUTO ? (f32 ? DCDL_CORR_BF16X3 : DCDL_CORR_F64) : want;
+  if (p < DCDL_CORR_F64 || p > DCDL_CORR_DIRECT) return -1;
+  if ((p == DCDL_CORR_BF16 || p == DCDL_CORR_BF16X3) && !f32) return -1;
+  if (p != DCDL_CORR_DIRECT && !mf_supported(g, mf_of(p))) p = DCDL_CORR_DIRECT;
+  return p;
+}
+
+// corr(Xin, D) at a resolved precision into CORR_BETA output `ob`; `pk`
+// holds D packed for that precision (mf_pack) unless DIRECT.
+template <class R>
+int corr_beta_at(hipStream_t stream, const Geom &g, int prec, const R *Xin, const R *D, const void *pk,
+                 const CorrOut &ob) {
+  if (prec == DCDL_CORR_DIRECT || !pk || !mf_supported(g, mf_of(prec)))
+    return run_corr<R, R, R, CORR_BETA>(stream, g, Xin, D, ob);
+  const int mp = mf_of(prec);
+  const MfPlan pl = mf_plan(g, mp);
+  if (mp == MF_F64) return run_corr_mfma<MF_F64, CORR_BETA, R, R>(stream, g, pl, Xin, pk, ob);
+  if constexpr (std::is_same<R, float>::value) {
+    if (mp == MF_BF16) return run_corr_mfma<MF_BF16, CORR_BETA, float, float>(stream, g, pl, Xin, pk, ob);
+    return run_corr_mfma<MF_BF16X3, CORR_BETA, float, float>(stream, g, pl, Xin, pk, ob);
+  }
+  return fail(DCDL_EINVAL, "the BF16 contractions need FP32 data");
+}
+
+// beta = corr(X, D) (Z = 0) at precision `prec` (a dcdl_corr_prec).
+template <class R>
+int beta_init(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, int want, R *beta) {
+  const int prec = resolve_prec(want, std::is_same<R, float>::value, g);
+  if (prec < 0) return fail(DCDL_EINVAL, "beta_prec %d is not available for this dtype", want);
+  CorrOut ob{};
+  ob.beta = beta;
+  void *pk = nullptr;
+  if (prec != DCDL_CORR_DIRECT) {
+    const int mp = mf_of(prec);
+    const MfPlan pl = mf_plan(g, mp);
+    WS("dpk_init", mf_pack_bytes(g, pl, mp), pk);
+    int rc = mf_pack<R>(stream, g, pl, mp, D, pk);
+    if (rc) return rc;
+  }
+  return corr_beta_at<R>(stream, g, prec, X, D, pk, ob);
+}
+
+// D packed for the FP64 matrix-core contraction in the "dpk64" slot, or NULL
+// when those atoms take the direct kernel.
+template <class R>
+int pack64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, void **out) {
+  *out = nullptr;
+  if (!mf_supported(g, MF_F64)) return DCDL_OK;
+  const MfPlan pl = mf_plan(g, MF_F64);
+  void *pk;
+  WS("dpk64", mf_pack_bytes(g, pl, MF_F64), pk);
+  int rc = mf_pack<R>(stream, g, pl, MF_F64, D, pk);
+  if (rc) return rc;
+  *out = pk;
+  return DCDL_OK;
+}
+
+// FP64 correlation of an FP64 signal: the FP64 matrix cores when `pk64` is
+// set, else the direct kernel.
+template <class Rz, int MODE>
+int corr64(hipStream_t stream, const Geom &g, const double *R64, const double *D64, const void *pk64,
+           const CorrOut &o) {
+  if (pk64 && mf_supported(g, MF_F64))
+    return run_corr_mfma<MF_F64, MODE, double, Rz>(stream, g, mf_plan(g, MF_F64), R64, pk64, o);
+  return run_corr<double, double, Rz, MODE>(stream, g, R64, D64, o);
+}
+
 // FP64 residual res = X - Z*D of a position-major z, enqueued without host
 // synchronisation; acc[0] += sum |z|, acc[1] += nnz (acc must start at 0).
 template <class R>
@@ -215,7 +293,9 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.lambda = lambda;
   o.positive = positive;
   o.result = scal + 1;
-  rc = run_corr<double, double, R, CORR_KKT>(stream, g, res, D64, o);
+  void *pk64;
+  if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
+  rc = corr64<R, CORR_KKT>(stream, g, res, D64, pk64, o);
   if (rc) return rc;
   double h[4];
   HIPCK(hipMemcpyAsync(h, scal, 32, hipMemcpyDeviceToHost, stream));
@@ -247,7 +327,10 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   ob.beta = beta;
   ob.zpm = zpm;
   ob.nrm = nrm64;
-  return run_corr<double, double, R, CORR_BETA>(stream, g, res, D64, ob);
+  void *pk64;
+  int rc = pack64<R>(ds, stream, g, D, &pk64);
+  if (rc) return rc;
+  return corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
 }
 
 // Exact FP64 norms from D.
@@ -397,9 +480,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
   } else {
     HIPCK(hipMemsetAsync(zpm, 0, sizeof(R) * nz, stream));
-    CorrOut ob{};
-    ob.beta = beta;
-    if ((rc = run_corr<R, R, R, CORR_BETA>(stream, g, X, D, ob))) return rc;
+    if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta))) return rc;
   }
   const R lam = (R)o->lambda, tol = (R)o->tol;
   hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam, tol,
@@ -563,6 +644,21 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   return status;
 }
 
+template <class R>
+int corr_impl(DeviceState *ds, hipStream_t stream, Geom g, const R *X, const R *D, R *out, int prec) {
+  g.KS = atom_stride(g.K, (int)sizeof(R));
+  const long long HW = (long long)g.H * g.W;
+  R *gpm;
+  WS("corr_pm", sizeof(R) * HW * g.KS, gpm);
+  int rc = beta_init<R>(ds, stream, g, X, D, prec, gpm);
+  if (rc) return rc;
+  hipLaunchKernelGGL((to_atom_major<R, R>), dim3(blocks_for(HW, 256)), dim3(256), 0, stream, (int)HW, g.K, g.KS, gpm,
+                     out);
+  HIPCK(hipGetLastError());
+  HIPCK(hipStreamSynchronize(stream));
+  return DCDL_OK;
+}
+
 struct Guard {
   DeviceState *ds;
   explicit Guard(DeviceState *d) : ds(d) { ds->mu.lock(); }
@@ -655,7 +751,9 @@ int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X
   CorrOut o{};
   o.positive = positive;
   o.result = scal;
-  if ((rc = run_corr<double, double, double, CORR_ABSMAX>(stream, g, X64, D64, o))) return rc;
+  void *pk64;
+  if ((rc = pack64<double>(ds, stream, g, D64, &pk64))) return rc;
+  if ((rc = corr64<double, CORR_ABSMAX>(stream, g, X64, D64, pk64, o))) return rc;
   HIPCK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
   return DCDL_OK;
@@ -681,6 +779,21 @@ int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dc
     return csc_impl<float>(ds, stream, g, shape->ndim, (const float *)X, (const float *)D, opts, (float *)z_out, info);
   return csc_impl<double>(ds, stream, g, shape->ndim, (const double *)X, (const double *)D, opts, (double *)z_out,
                           info);
+}
+
+int dicodile_corr(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D, void *out, int32_t prec,
+                  void *stream_) {
+  Geom g;
+  int rc = make_geom(shape, &g);
+  if (rc) return rc;
+  if (!X || !D || !out) return fail(DCDL_EINVAL, "NULL pointer");
+  if (dtype != DCDL_F32 && dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
+  if (prec < DCDL_CORR_AUTO || prec > DCDL_CORR_DIRECT) return fail(DCDL_EINVAL, "unknown precision %d", prec);
+  if (dtype == DCDL_F64 && (prec == DCDL_CORR_BF16 || prec == DCDL_CORR_BF16X3))
+    return fail(DCDL_EINVAL, "the BF16 contractions need FP32 data");
+  PROLOGUE();
+  if (dtype == DCDL_F32) return corr_impl<float>(ds, stream, g, (const float *)X, (const float *)D, (float *)out, prec);
+  return corr_impl<double>(ds, stream, g, (const double *)X, (const double *)D, (double *)out, prec);
 }
 
 int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, const void *D, const void *z,

@@ -1,0 +1,276 @@
+// dcdl_mfma.h -- the dense correlation G = corr(R, D) on the CDNA matrix cores.
+//
+// G_k[pos] = sum_p sum_t D_{k,p}[t] R_p[pos + t] (the paper's R * D~_k, used by
+// beta = corr(X - Z*D, D) + n z of Sec. 3 and by the optimality check) is a
+// product of the atom matrix D (K x P|Theta|) with the windows of R: rows are
+// atoms, columns are positions, the reduction runs over (t1, channel chunk,
+// t2, channel).  One workgroup computes TR rows x TC columns of positions for
+// up to 64 atoms; each of its four waves owns NTW 16-position column tiles.
+//
+//   * the atom operand comes from a packed copy of D laid out so that every
+//     lane's fragment of one MFMA step is one coalesced load;
+//   * the window operand is staged in LDS as [row][column][channel] for one t1
+//     and one chunk of PC channels, so a lane's fragment (consecutive
+//     reduction indices) is contiguous in LDS;
+//   * F64: v_mfma_f64_16x16x4 (FP64 products and sums, the precision of the
+//     final check and the drift correction);  BF16: v_mfma_f32_16x16x32_bf16
+//     (BF16 operands, FP32 accumulation);  BF16X3: the same instruction on
+//     hi/lo BF16 splits of both operands (hi*hi + hi*lo + lo*hi), close to
+//     FP32 accuracy at three BF16 products.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dcdl_kernels.h"
+
+namespace dcdl {
+
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 mf_bf8 __attribute__((ext_vector_type(8)));
+
+enum MfPrec { MF_F64 = 0, MF_BF16 = 1, MF_BF16X3 = 2 };
+
+template <int PREC> struct MfT;
+template <> struct MfT<MF_F64> {
+  using In = double;   // operand element
+  using Acc = double;  // accumulator element
+  using C4 = mf_d4;
+  static constexpr int KK = 4;      // reduction length of one instruction
+  static constexpr int NCOPY = 1;   // operand copies (hi, lo)
+};
+template <> struct MfT<MF_BF16> {
+  using In = __bf16;
+  using Acc = float;
+  using C4 = mf_f4;
+  static constexpr int KK = 32;
+  static constexpr int NCOPY = 1;
+};
+template <> struct MfT<MF_BF16X3> {
+  using In = __bf16;
+  using Acc = float;
+  using C4 = mf_f4;
+  static constexpr int KK = 32;
+  static constexpr int NCOPY = 2;
+};
+
+// Layout of the packed dictionary and of the reduction.
+struct MfPlan {
+  int PC;    // channels per chunk (1, 2, 4 or 8)
+  int NPC;   // channel chunks
+  int L2p;   // t2 extent padded so that L2p * PC is a multiple of the instruction's reduction
+  int SPS;   // instruction steps per (t1, chunk) stage = L2p * PC / KK
+  int MTT;   // 16-atom tiles in total = ceil(K / 16)
+};
+
+// Packed atom operand: for stage (t1, chunk), step s, atom tile m and lane l,
+// the KK/4 values D[16 m + l % 16][p][t1][t2] at reduction indices
+// rl = s KK + (l / 16) (KK / 4) + e, (t2, pp) = divmod(rl, PC), p = chunk PC + pp;
+// zero outside the atoms, channels and taps.  Copy 1 (BF16X3) holds the low
+// halves d - bf16(d).
+template <int PREC, class Rd>
+__global__ __launch_bounds__(256) void mf_pack_dict(Geom g, MfPlan pl, const Rd *__restrict__ D,
+                                                    typename MfT<PREC>::In *__restrict__ out, long long n) {
+  using T = MfT<PREC>;
+  constexpr int VPL = T::KK / 4;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const int e = (int)(i % VPL);
+    long long q = i / VPL;
+    const int lane = (int)(q % 64);
+    q /= 64;
+    const int m = (int)(q % pl.MTT);
+    q /= pl.MTT;
+    const int s = (int)(q % pl.SPS);
+    q /= pl.SPS;
+    const int pc = (int)(q % pl.NPC);
+    const int t1 = (int)(q / pl.NPC);
+    const int rl = s * T::KK + (lane / 16) * VPL + e;
+    const int t2 = rl / pl.PC, pp = rl - (rl / pl.PC) * pl.PC;
+    const int k = 16 * m + lane % 16, p = pc * pl.PC + pp;
+    double v = 0.0;
+    if (k < g.K && p < g.P && t2 < g.L2) v = (double)D[(((long long)k * g.P + p) * g.L1 + t1) * g.L2 + t2];
+    if constexpr (PREC == MF_F64) {
+      out[i] = (typename T::In)v;
+    } else {
+      const __bf16 hi = (__bf16)(float)v;
+      out[i] = hi;
+      if constexpr (T::NCOPY == 2) out[n + i] = (__bf16)((float)v - (float)hi);
+    }
+  }
+}
+
+template <int PREC>
+__device__ __forceinline__ typename MfT<PREC>::C4 mf_step(typename MfT<PREC>::C4 c, const void *a, const void *b);
+
+template <>
+__device__ __forceinline__ mf_d4 mf_step<MF_F64>(mf_d4 c, const void *a, const void *b) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(*reinterpret_cast<const double *>(a),
+                                              *reinterpret_cast<const double *>(b), c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ mf_f4 mf_step<MF_BF16>(mf_f4 c, const void *a, const void *b) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(*reinterpret_cast<const mf_bf8 *>(a),
+                                                 *reinterpret_cast<const mf_bf8 *>(b), c, 0, 0, 0);
+}
+
+// A lane's window fragment: KK/4 consecutive elements at an alignment of
+// PC elements (a whole fragment when PC * size >= 16 bytes).
+template <int PREC, int PC>
+__device__ __forceinline__ void mf_load_b(const typename MfT<PREC>::In *p, typename MfT<PREC>::In *dst) {
+  using In = typename MfT<PREC>::In;
+  constexpr int VPL = MfT<PREC>::KK / 4;
+  if constexpr (VPL == 1) {
+    dst[0] = p[0];
+  } else {
+    constexpr int CH = PC * (int)sizeof(In) >= 16 ? VPL : PC;  // elements per aligned piece
+#pragma unroll
+    for (int c = 0; c < VPL; c += CH) {
+      if (CH * sizeof(In) == 16)
+        *reinterpret_cast<uint4 *>(dst + c) = *reinterpret_cast<const uint4 *>(p + c);
+      else if (CH * sizeof(In) == 8)
+        *reinterpret_cast<uint2 *>(dst + c) = *reinterpret_cast<const uint2 *>(p + c);
+      else if (CH * sizeof(In) == 4)
+        *reinterpret_cast<uint32_t *>(dst + c) = *reinterpret_cast<const uint32_t *>(p + c);
+      else
+        *reinterpret_cast<uint16_t *>(dst + c) = *reinterpret_cast<const uint16_t *>(p + c);
+    }
+  }
+}
+
+// TR x (4 NTW 16 / TR) positions per workgroup: TR = 1 for signals (the four
+// waves side by side along the row), TR = 4 for images (one row per wave).
+// PC = 0 takes the channel chunk from the plan (FP64, one element per lane).
+template <int PREC, int MODE, int TR, int NTW, int MT, int PC, class Rin, class Rz>
+__global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *__restrict__ X,
+                                                 const typename MfT<PREC>::In *__restrict__ Dpk, long long npk,
+                                                 int m0, CorrOut o) {
+  using T = MfT<PREC>;
+  using In = typename T::In;
+  using Acc = typename T::Acc;
+  constexpr int VPL = T::KK / 4;
+  constexpr int TC = (4 / TR) * NTW * 16;  // positions per row
+  extern __shared__ __align__(16) unsigned char mf_smem[];
+  In *xs = reinterpret_cast<In *>(mf_smem);
+  const int pcs = PC > 0 ? PC : pl.PC;
+  const int TCX = TC + pl.L2p;  // staged columns
+  const int row_elems = TCX * pcs;
+  const int copy_elems = TR * row_elems;
+  __shared__ double sh_red[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int h0 = blockIdx.y * TR, w0 = blockIdx.x * TC;
+  const int wr = TR == 1 ? 0 : wave;                      // row of this wave in the tile
+  const int wc = TR == 1 ? wave * NTW * 16 : 0;           // first column of this wave
+  const long long plane = (long long)g.T1 * g.T2;
+
+  typename T::C4 acc[MT][NTW];
+#pragma unroll
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int n = 0; n < NTW; ++n) acc[m][n] = typename T::C4{0, 0, 0, 0};
+
+  for (int t1 = 0; t1 < g.L1; ++t1)
+    for (int pc = 0; pc < pl.NPC; ++pc) {
+      __syncthreads();
+      // stage rows h0 + t1 + r, columns w0 + c, channels pc PC + pp
+      for (int e = tid; e < copy_elems; e += 256) {
+        const int c = e % TCX, rest = e / TCX;
+        const int pp = rest % pcs, r = rest / pcs;
+        const int p = pc * pcs + pp, hh = h0 + t1 + r, ww = w0 + c;
+        double v = 0.0;
+        if (p < g.P && hh < g.T1 && ww < g.T2) v = (double)X[p * plane + (long long)hh * g.T2 + ww];
+        const int li = r * row_elems + c * pcs + pp;
+        if constexpr (PREC == MF_F64) {
+          xs[li] = (In)v;
+        } else {
+          const __bf16 hi = (__bf16)(float)v;
+          xs[li] = hi;
+          if constexpr (T::NCOPY == 2) xs[copy_elems + li] = (__bf16)((float)v - (float)hi);
+        }
+      }
+      __syncthreads();
+      const long long sbase = ((long long)(t1 * pl.NPC + pc) * pl.SPS) * pl.MTT;
+      const In *xrow = xs + wr * row_elems;
+      for (int s = 0; s < pl.SPS; ++s) {
+        In a[T::NCOPY][MT][VPL];
+#pragma unroll
+        for (int m = 0; m < MT; ++m) {
+          const long long ai = ((sbase + (long long)s * pl.MTT + m0 + m) * 64 + lane) * VPL;
+#pragma unroll
+          for (int cp = 0; cp < T::NCOPY; ++cp) {
+            if constexpr (VPL == 1)
+              a[cp][m][0] = Dpk[cp * npk + ai];
+            else
+              *reinterpret_cast<uint4 *>(a[cp][m]) = *reinterpret_cast<const uint4 *>(Dpk + cp * npk + ai);
+          }
+        }
+        const int rl = s * T::KK + (lane >> 4) * VPL;  // first reduction index of this lane
+#pragma unroll
+        for (int n = 0; n < NTW; ++n) {
+          const int col = wc + n * 16 + (lane & 15);
+          In b[T::NCOPY][VPL];
+#pragma unroll
+          for (int cp = 0; cp < T::NCOPY; ++cp) mf_load_b<PREC, PC>(xrow + cp * copy_elems + col * pcs + rl, b[cp]);
+#pragma unroll
+          for (int m = 0; m < MT; ++m) {
+            if constexpr (PREC == MF_F64) {
+              acc[m][n] = mf_step<MF_F64>(acc[m][n], a[0][m], b[0]);
+            } else {
+              acc[m][n] = mf_step<MF_BF16>(acc[m][n], a[0][m], b[0]);
+              if constexpr (T::NCOPY == 2) {
+                acc[m][n] = mf_step<MF_BF16>(acc[m][n], a[0][m], b[1]);
+                acc[m][n] = mf_step<MF_BF16>(acc[m][n], a[1][m], b[0]);
+              }
+            }
+          }
+        }
+      }
+    }
+
+  // epilogue: register v of a lane holds position column (lane % 16) and, in
+  // the 16-atom tile, row (lane / 16) + 4 v for the FP64 instruction and row
+  // 4 (lane / 16) + v for the BF16 one
+  double red = 0.0;
+  const int hh = h0 + wr;
+#pragma unroll
+  for (int n = 0; n < NTW; ++n) {
+    const int ww = w0 + wc + n * 16 + (lane & 15);
+    if (hh >= g.H || ww >= g.W) continue;
+    const long long pos = (long long)hh * g.W + ww;
+#pragma unroll
+    for (int m = 0; m < MT; ++m)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = 16 * (m0 + m) + (PREC == MF_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
+        const double gv = (double)acc[m][n][v];
+        if (MODE == CORR_BETA) {
+          if (k < g.K) {
+            double bv = gv;
+            if (o.zpm) bv += o.nrm[k] * (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+            reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = (Rz)bv;
+          } else if (k < g.KS) {
+            reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = Rz(0);
+          }
+        } else if (k < g.K) {
+          if (MODE == CORR_KKT) {
+            const double z = (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+            double vv;
+            if (z == 0.0)
+              vv = o.positive ? fmax(gv - o.lambda, 0.0) : fmax(fabs(gv) - o.lambda, 0.0);
+            else
+              vv = fabs(gv - (z > 0.0 ? o.lambda : -o.lambda));
+            red = fmax(red, vv);
+          } else {
+            red = fmax(red, o.positive ? gv : fabs(gv));
+          }
+        }
+      }
+  }
+  if (MODE != CORR_BETA) {
+    red = block_max<256>(red, sh_red);
+    if (tid == 0) atomic_max_nonneg(o.result, fmax(red, 0.0));
+  }
+}
+
+}  // namespace dcdl

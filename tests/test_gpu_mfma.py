@@ -1,0 +1,122 @@
+"""The matrix-core correlation G = corr(X, D) in each precision against the
+FP64 oracle, element by element, within error bounds derived from the
+arithmetic of each path (absC = corr(|X|, |D|), n = P L1 L2 terms):
+
+  F64     products and sums in FP64:           |err| <= 2 n 2^-53 absC
+  BF16    operands rounded to BF16 (2^-9 each), FP32 sums:
+                                               |err| <= (2^-8 + n 2^-23) absC
+  BF16X3  hi/lo splits, hi*hi + hi*lo + lo*hi: each product off by at most
+          |xl dl| + the split remainders (<= 3 2^-17 relative), FP32 sums:
+                                               |err| <= (3 2^-17 + 3 n 2^-23) absC
+  DIRECT  FP32 (or FP64) FMA chain:            |err| <= n 2^-23 absC (2^-52)
+
+Shapes span several workgroup tiles with ragged tails, atom counts above 64
+(two atom groups), channel counts that are padded (P = 3, 5) and taps that
+are padded (L = 250, 12)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09235_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1901_09235_amd as dl
+    dl.load()
+    return dl
+
+
+def dev(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+CASES = {
+    # name: (P, T, K, L)
+    "serving_like": (32, 1000, 40, 128),
+    "signal_p1": (1, 3000, 5, 64),
+    "paper_1d": (7, 1400, 25, 250),
+    "atoms70": (2, 700, 70, 20),
+    "image_p1": (1, (70, 83), 25, (16, 16)),
+    "rgb": (3, (75, 90), 25, (32, 32)),
+    "image_p5_L12": (5, (41, 150), 16, (12, 12)),
+}
+
+
+def _case(name, seed=5):
+    P, T, K, L = CASES[name]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    D = synth.gaussian_dictionary(rng, K, P, L)
+    shape = (P, T) if isinstance(T, int) else (P,) + tuple(T)
+    X = rng.standard_normal(shape)
+    return X, D
+
+
+def _bound(prec, n, absC):
+    u = 2.0 ** -53
+    if prec == "f64":
+        return 2 * n * u * absC + 1e-300
+    if prec == "bf16":
+        return (2.0 ** -8 + n * 2.0 ** -23) * absC
+    if prec == "bf16x3":
+        return (3 * 2.0 ** -17 + 3 * n * 2.0 ** -23) * absC
+    return n * 2.0 ** -23 * absC
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "bf16", "bf16x3", "direct"])
+def test_corr_fp32_data_within_bound(lib, name, prec):
+    X, D = _case(name)
+    X32, D32 = X.astype(np.float32).astype(np.float64), D.astype(np.float32).astype(np.float64)
+    G = lib.dicodile_corr(dev(X32, torch.float32), dev(D32, torch.float32), prec=prec).double().cpu().numpy()
+    ref = oracle.corr(X32, D32)
+    absC = oracle.corr(np.abs(X32), np.abs(D32))
+    n = D.size // D.shape[0]
+    # the FP32 output rounding adds 2^-24 |G|
+    bound = _bound(prec, n, absC) + 2.0 ** -24 * np.abs(ref)
+    err = np.abs(G - ref)
+    assert G.shape == ref.shape
+    assert np.all(err <= bound), (name, prec, float(np.max(err / np.maximum(absC, 1e-300))))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("prec", ["f64", "direct"])
+def test_corr_fp64_data_within_bound(lib, name, prec):
+    X, D = _case(name, seed=6)
+    G = lib.dicodile_corr(dev(X, torch.float64), dev(D, torch.float64), prec=prec).cpu().numpy()
+    ref = oracle.corr(X, D)
+    absC = oracle.corr(np.abs(X), np.abs(D))
+    n = D.size // D.shape[0]
+    err = np.abs(G - ref)
+    assert np.all(err <= 2 * n * 2.0 ** -53 * absC + 1e-300), (name, prec)
+
+
+def test_bf16_is_rejected_for_fp64_data(lib):
+    X, D = _case("signal_p1")
+    with pytest.raises(lib.DicodileError):
+        lib.dicodile_corr(dev(X, torch.float64), dev(D, torch.float64), prec="bf16")
+
+
+@pytest.mark.parametrize("beta_prec", ["f64", "bf16", "bf16x3", "direct"])
+def test_solve_reaches_oracle_with_each_init_precision(lib, beta_prec):
+    """Whatever contraction initialises beta, the FP32 solve ends at the
+    oracle's minimiser: a BF16 start is corrected by the FP64 drift pass."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(9)), 8, 4, 32)
+    pb = synth.make_problem("p", 901, P=4, T=4000, K=8, L=32, rho=0.004, amp="exp", sigma=0.1, D=D)
+    X = pb.X.astype(np.float32).astype(np.float64)
+    Dd = D.astype(np.float32).astype(np.float64)
+    lam = 0.1 * oracle.lambda_max(X, Dd)
+    z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
+                               beta_prec=beta_prec, max_polish=4)
+    assert info["status"] == "OK", info
+    Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
+    fo = oracle.objective(X, Dd, Zo, lam)
+    fg = oracle.objective(X, Dd, z.double().cpu().numpy(), lam)
+    assert (fg - fo) / fo <= 1e-6
+    assert oracle.kkt(X, Dd, z.double().cpu().numpy(), lam) <= 1e-4
