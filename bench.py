@@ -55,9 +55,12 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="image_1024",
-                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images", "serving"])
-    ap.add_argument("--requests", type=int, default=400, help="requests of the serving workload")
-    ap.add_argument("--pool", type=int, default=24, help="distinct request signals of the serving workload")
+                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images", "serving", "corr"])
+    ap.add_argument("--requests", type=int, default=2000, help="measured requests of the serving workload")
+    ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up requests of the serving workload")
+    ap.add_argument("--pool", type=int, default=48, help="distinct request signals of the serving workload")
+    ap.add_argument("--budgets", default="0,2048,512",
+                    help="serving: HBM admission budgets in MiB to sweep (0: the server default)")
     ap.add_argument("--rate", type=float, default=200.0, help="Poisson arrival rate of the serving workload")
     ap.add_argument("--max-workers", type=int, default=0, help="server: workgroups per request at most")
     ap.add_argument("--slice", type=int, default=0, help="server: rounds per launch")
@@ -69,6 +72,7 @@ def parse():
     ap.add_argument("--grid", type=int, nargs="*", default=None)
     ap.add_argument("--tile", type=int, nargs="*", default=None)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true", help="batch: skip the autotuner (defaults)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128, help="side of the oracle's crop")
     ap.add_argument("--probe-mib", type=int, default=1024, help="copy-probe size (0: skip)")
@@ -134,10 +138,15 @@ def run_batch(args):
     zs = [torch.empty((D.shape[0], X.shape[1] - D.shape[2] + 1, X.shape[2] - D.shape[3] + 1),
                       dtype=torch.float32, device="cuda") for X in Xs]
     bopts = {}
-    if args.threads:
-        bopts["threads"] = args.threads
-    if args.tile:
-        bopts["tile"] = tuple(args.tile) if len(args.tile) > 1 else args.tile[0]
+    tune = None
+    if args.threads or args.tile:
+        if args.threads:
+            bopts["threads"] = args.threads
+        if args.tile:
+            bopts["tile"] = tuple(args.tile) if len(args.tile) > 1 else args.tile[0]
+    elif not args.no_autotune:
+        bopts, tune = dl.dicodile_csc_batch_autotune(Xs, D, lams, tols)
+        print(f"# autotuned {bopts} in {tune['t_tune_s']:.1f} s", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs, **bopts)
     torch.cuda.synchronize()
@@ -176,6 +185,8 @@ def run_batch(args):
                              "check": binfos[-1]["t_check_s"] * 1e3},
         "workers": binfos[-1]["workers"], "launches": binfos[-1]["n_passes"],
         "used_graph": binfos[-1]["used_graph"],
+        "batch_opts": {k: (list(v) if isinstance(v, tuple) else v) for k, v in bopts.items()},
+        "autotune": tune,
         "plain_s_for_all": t_plain,
         "plain_instances_timed": n_plain,
         "batched_over_plain": (t_plain / dt) if t_plain else None,
@@ -194,8 +205,11 @@ def _percentiles(v):
 def run_serving(args):
     """Serving pattern: Poisson arrivals of multichannel 1-D requests of
     log-uniform length sharing one dictionary, served by continuous batching
-    (dicodile_server_*), beside the plain form: the same arrivals solved one
-    call at a time in arrival order.  Latency = arrival -> z ready."""
+    (dicodile_server_*) under a sweep of HBM admission budgets, beside the
+    plain form: the same arrivals solved one call at a time in arrival order.
+    Latency = arrival -> z ready.  The request signals come from a pool of
+    distinct seeded requests, reused cyclically; every request is solved in
+    full into its own output."""
     import threading
     import numpy as np
     import torch
@@ -211,64 +225,74 @@ def run_serving(args):
     Xs = [torch.from_numpy(pb.X).to("cuda", dtype=torch.float32).contiguous() for pb in pool]
     lams = [pb.lambda_frac * dl.dicodile_lambda_max(X, D) for pb, X in zip(pool, Xs)]
     L = D.shape[2]
-    arrivals = synth.serving_arrivals(args.requests, rate_hz=args.rate)
-    which = [i % len(pool) for i in range(args.requests)]
-    zs = [torch.empty((D.shape[0], Xs[j].shape[1] - L + 1), dtype=torch.float32, device="cuda") for j in which]
+    n_warm, n_meas = args.serve_warmup, args.requests
+    arrivals = synth.serving_arrivals(n_warm + n_meas, rate_hz=args.rate)
+    which = [i % len(pool) for i in range(n_warm + n_meas)]
+    # one output per in-flight request: a ring deep enough for any backlog here
+    ring = min(len(which), 512)
+    zs = [torch.empty((D.shape[0], Xs[which[i]].shape[1] - L + 1), dtype=torch.float32, device="cuda")
+          for i in range(ring)]
     torch.cuda.synchronize()
     max_len = max(X.shape[1] for X in Xs)
-    sopts = dict(hbm_budget_bytes=32 << 30, max_len=max_len)
-    if args.max_workers:
-        sopts["max_workers"] = args.max_workers
-    if args.slice:
-        sopts["slice_rounds"] = args.slice
 
-    srv = dl.Server(D, **sopts)
-    try:
-        # warm-up: every pool signal once, all at once
-        tk = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
-        warm = [srv.wait(t) for t in tk]
-        for z, info in warm:
-            if info["status"] != "OK":
-                raise SystemExit(f"served warm-up request did not converge: {info}")
-        print("# warm-up done", file=sys.stderr, flush=True)
-        st0 = srv.stats()
-        results = [None] * args.requests
-        tickets = [None] * args.requests
-        sub_at = [0.0] * args.requests
+    def serve(budget_mib):
+        sopts = dict(max_len=max_len)
+        if budget_mib > 0:
+            sopts["hbm_budget_bytes"] = budget_mib << 20
+        if args.max_workers:
+            sopts["max_workers"] = args.max_workers
+        if args.slice:
+            sopts["slice_rounds"] = args.slice
+        srv = dl.Server(D, **sopts)
+        n = n_warm + n_meas
+        results, tickets, sub_at = [None] * n, [None] * n, [0.0] * n
         ready = threading.Semaphore(0)
 
         def collect():
-            for i in range(args.requests):
+            for i in range(n):
                 ready.acquire()
                 results[i] = srv.wait(tickets[i])[1]
-        th = threading.Thread(target=collect)
-        th.start()
-        start = time.monotonic() + 0.05
-        for i in range(args.requests):
-            delay = start + arrivals[i] - time.monotonic()
-            if delay > 0:
-                time.sleep(delay)
-            sub_at[i] = time.monotonic()
-            j = which[i]
-            tickets[i] = srv.submit(Xs[j], lams[j], 1e-5 * lams[j], z_out=zs[i])
-            ready.release()
-        th.join()
-        st1 = srv.stats()
-    finally:
-        srv.close()
-    lat = [(sub_at[i] - (start + arrivals[i])) + results[i]["t_total_s"] for i in range(args.requests)]
-    done_at = [sub_at[i] + results[i]["t_total_s"] for i in range(args.requests)]
-    span = max(done_at) - (start + arrivals[0])
-    bad = [r for r in results if r["status"] != "OK"]
-    if bad:
-        raise SystemExit(f"{len(bad)} served requests did not converge: {bad[0]}")
-    served_obj = {}
-    for i, r in enumerate(results):
-        served_obj.setdefault(which[i], r["objective"])
-    print(f"# served {args.requests} requests in {span:.2f} s", file=sys.stderr, flush=True)
+        try:
+            th = threading.Thread(target=collect)
+            th.start()
+            start = time.monotonic() + 0.05
+            for i in range(n):
+                if i >= ring:  # the output slot is reused: its earlier request must be done
+                    while results[i - ring] is None:
+                        time.sleep(1e-4)
+                delay = start + arrivals[i] - time.monotonic()
+                if delay > 0:
+                    time.sleep(delay)
+                sub_at[i] = time.monotonic()
+                j = which[i]
+                tickets[i] = srv.submit(Xs[j], lams[j], 1e-5 * lams[j], z_out=zs[i % ring])
+                ready.release()
+            th.join()
+            st = srv.stats()
+        finally:
+            srv.close()
+        meas = range(n_warm, n)
+        bad = [results[i] for i in meas if results[i]["status"] != "OK"]
+        if bad:
+            raise SystemExit(f"{len(bad)} served requests did not converge: {bad[0]}")
+        lat = [(sub_at[i] - (start + arrivals[i])) + results[i]["t_total_s"] for i in meas]
+        done = [sub_at[i] + results[i]["t_total_s"] for i in meas]
+        span = max(done) - (start + arrivals[n_warm])
+        out = dict(_percentiles(lat), requests_per_s=n_meas / span, budget_mib=budget_mib or "default",
+                   max_kkt=max(results[i]["kkt"] for i in meas),
+                   queue_p99_ms=_percentiles([results[i]["t_init_s"] for i in meas])["p99_ms"],
+                   peak_active=st["peak_active"], peak_workers=st["peak_workers"], launches=st["n_launches"],
+                   rounds_busy_frac=st["t_rounds_s"] / max(1e-9, st["t_busy_s"]))
+        obj = {which[i]: results[i]["objective"] for i in meas}
+        print(f"# served {n_meas} requests, budget {budget_mib} MiB: {out['requests_per_s']:.1f} req/s, "
+              f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        return out, obj
+
+    sweeps = [serve(int(b)) for b in args.budgets.split(",")]
+    served, served_obj = sweeps[0]
 
     # plain form: one dicodile_csc call per request, in arrival order
-    n_plain = args.requests if args.plain < 0 else min(args.plain, args.requests)
+    n_plain = n_meas if args.plain < 0 else min(args.plain, n_meas)
     plain = None
     gap = 0.0
     if n_plain > 0:
@@ -282,14 +306,15 @@ def run_serving(args):
             if delay > 0:
                 time.sleep(delay)
             j = which[i]
-            _, info = dl.dicodile_csc(Xs[j], D, lams[j], 1e-5 * lams[j], z_out=zs[i],
+            _, info = dl.dicodile_csc(Xs[j], D, lams[j], 1e-5 * lams[j], z_out=zs[i % ring],
                                       max_rounds=50_000_000, timeout_s=120)
             if info["status"] != "OK":
                 raise SystemExit(f"plain solve did not converge: {info}")
             now = time.monotonic()
             plat.append(now - (start + arrivals[i]))
             pdone.append(now)
-            gap = max(gap, abs(info["objective"] - served_obj[j]) / info["objective"])
+            if j in served_obj:
+                gap = max(gap, abs(info["objective"] - served_obj[j]) / info["objective"])
         pspan = pdone[-1] - (start + arrivals[0])
         plain = dict(_percentiles(plat), requests=n_plain, requests_per_s=n_plain / pspan)
         print(f"# plain form: {n_plain} requests in {pspan:.2f} s", file=sys.stderr, flush=True)
@@ -297,27 +322,94 @@ def run_serving(args):
     lens = [Xs[j].shape[1] for j in which]
     out = {
         "metric": "served requests/s with p50/p99 latency (arrival -> z at KKT tol), continuous batching vs plain",
-        "value": args.requests / span, "unit": "requests/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-        "ms_per_step": span * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "value": served["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": n_meas,
+        "warmup": n_warm, "ms_per_step": 1e3 / served["requests_per_s"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"serving_poisson{args.rate:g}_P32_K40_L128_T1e4-5e5",
-                   "requests": args.requests, "distinct_signals": len(pool), "offered_rate_hz": args.rate,
-                   "lambda": "0.2 lambda_max each", "tol": "1e-5 lambda each", "mean_T": float(np.mean(lens))},
-        "served": dict(_percentiles(lat), requests_per_s=args.requests / span),
+                   "requests": n_meas, "warmup_requests": n_warm, "distinct_signals": len(pool),
+                   "offered_rate_hz": args.rate, "lambda": "0.2 lambda_max each", "tol": "1e-5 lambda each",
+                   "mean_T": float(np.mean(lens))},
+        "served": served,
+        "budget_sweep": [sw for sw, _ in sweeps],
         "plain": plain,
-        "served_over_plain_throughput": (args.requests / span) / plain["requests_per_s"] if plain else None,
+        "served_over_plain_throughput": served["requests_per_s"] / plain["requests_per_s"] if plain else None,
         "max_objective_gap_served_vs_plain": gap if plain else None,
-        "max_kkt": max(r["kkt"] for r in results),
-        "queue_ms": _percentiles([r["t_init_s"] for r in results]),
-        "server": {k: st1[k] - st0.get(k, 0) if k in ("n_launches", "t_rounds_s", "t_busy_s", "n_done") else st1[k]
-                   for k in st1},
         "generation_s": t_gen,
     }
     print(json.dumps(out), flush=True)
 
+MFMA_PEAK_TFS = {"f64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0 / 3, "direct": 157.3}
+
+
+def run_corr_bench(args):
+    """The dense contraction G = corr(X, D) (beta initialisation, drift
+    correction, KKT check) in each precision on the workloads' shapes: call
+    time (HIP events around the call on its stream), algorithmic TFLOP/s
+    (2 K P |Theta| per valid position) and the error of each precision
+    against the FP64 contraction on the same data."""
+    import torch
+    import paper_1901_09235_amd as dl
+    shapes = {
+        "serving_max_P32_T500000_K40_L128": (32, (500000,), 40, (128,)),
+        "image_rgb_4096_K25_L32": (3, (4096, 4096), 25, (32, 32)),
+        "image_1024_K25_L16": (1, (1024, 1024), 25, (16, 16)),
+    }
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    res = {}
+    for name, (P, T, K, L) in shapes.items():
+        X = torch.randn((P,) + T, generator=gen, device="cuda", dtype=torch.float32)
+        D = torch.randn((K, P) + L, generator=gen, device="cuda", dtype=torch.float32)
+        D /= D.flatten(1).norm(dim=1).view((K,) + (1,) * (D.dim() - 1))
+        positions = 1
+        for t, l in zip(T, L):
+            positions *= t - l + 1
+        flop = 2.0 * K * P * positions * int(torch.tensor(L).prod())
+        out = {}
+        ref = None
+        for prec in ("f64", "bf16x3", "bf16", "direct"):
+            if prec == "direct" and flop > 2e11:
+                continue
+            G = dl.dicodile_corr(X, D, prec=prec)  # warm-up
+            torch.cuda.synchronize()
+            reps = 3
+            st = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            for _ in range(reps):
+                dl.dicodile_corr(X, D, prec=prec, out=G, stream=st.cuda_stream)
+            e1.record(st)
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tfs = flop / (ms * 1e-3) / 1e12
+            rec = {"ms": ms, "tflops": tfs, "peak_tflops": MFMA_PEAK_TFS[prec], "frac": tfs / MFMA_PEAK_TFS[prec]}
+            if prec == "f64":
+                ref = G.double()
+            else:
+                rec["max_err_rel_to_max"] = float((G.double() - ref).abs().max() / ref.abs().max())
+            out[prec] = rec
+            print(f"# {name} {prec}: {ms:.3f} ms, {tfs:.1f} TFLOP/s", file=sys.stderr, flush=True)
+            del G
+        res[name] = {"gflop": flop / 1e9, "precisions": out}
+        del X, D
+        torch.cuda.empty_cache()
+    best = res["serving_max_P32_T500000_K40_L128"]["precisions"]["f64"]
+    line = {
+        "metric": "dense correlation corr(X, D) throughput on the matrix cores", "value": best["tflops"],
+        "unit": "TFLOP/s", "n_gpus": 1, "steps": 3, "warmup": 1, "ms_per_step": best["ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "corr_serving_max_P32_T500000_K40_L128"},
+        "roofline": {"bound": "mfma", "kernel": "corr_mfma<F64>", "achieved": best["tflops"], "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": best["tflops"] / 78.6, "traffic": None},
+        "shapes": res,
+    }
+    print(json.dumps(line), flush=True)
+
 
 def main():
     args = parse()
+    if args.workload == "corr" and args.gpus == 1:
+        return run_corr_bench(args)
     if args.workload == "serving" and args.gpus == 1:
         return run_serving(args)
     if args.workload == "batch_images" and args.gpus == 1:
@@ -415,6 +507,15 @@ def main():
             k: last[f"t_worker_{k}_s"] / max(1, last["n_rounds"]) * 1e6
             for k in ("wait", "select", "collect", "apply")},
     }
+    if args.workload == "image_rgb_4096":
+        L = D.shape[2:]
+        dl.dicodile_dict_stats(z, X, tuple(L))  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ztz, ztX = dl.dicodile_dict_stats(z, X, tuple(L))
+        torch.cuda.synchronize()
+        out["dict_stats_ms"] = (time.perf_counter() - t0) * 1e3
+        out["dict_stats_shapes"] = {"ztz": list(ztz.shape), "ztX": list(ztX.shape)}
     tr = stored_traffic(pb.name)
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]

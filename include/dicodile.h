@@ -96,8 +96,9 @@ typedef struct {
   int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
   int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library */
   int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
-  int32_t refresh_every;  /* recompute beta from its definition every this many sweeps
-                             (drift correction, FP64 contraction); 0 -> only at the end */
+  int32_t refresh_every;  /* rebuild beta from z every this many sweeps of rounds by the
+                             beta_prec contraction over the FP64 residual (the periodic refresh);
+                             0 -> never.  FP64 drift correction runs after a failed final check */
   int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
   int32_t inner;          /* sub-domain visits per worker per round; 0 -> 1 */
   int32_t beta_prec;      /* dcdl_corr_prec of the contraction that initialises beta from X
@@ -136,6 +137,9 @@ typedef struct {
   double t_worker_select_s;  /* ... selecting, soft-lock testing and publishing candidates */
   double t_worker_collect_s; /* ... waiting for the neighbours' candidates */
   double t_worker_apply_s;   /* ... applying accepted updates to beta, z and the move cache */
+  double beta_drift;         /* at the first FP64 check: max |beta kept by the rounds - (corr(X - Z*D, D)
+                                + n z) in FP64|, / lambda: the error of the incremental beta against
+                                its FP64 definition (NaN if no check ran) */
 } dcdl_csc_info;
 
 /* Library version string (static storage). */
@@ -230,7 +234,9 @@ typedef struct {
  * stopping consensus, Alg. 3).  All shapes share ndim, P, K and L; only T
  * differs.  X and z_out are host arrays of n device pointers; D is one device
  * pointer; opts holds n per-instance options (lambda, tol, positive, certify,
- * dtype, kkt_target; dtype must agree); infos (host, may be NULL) receives n
+ * dtype, kkt_target, timeout_s as a wall-clock cap on each round launch of
+ * that instance; dtype must agree; the first instance's beta_prec applies to
+ * all); infos (host, may be NULL) receives n
  * records.  Returns DCDL_OK if every instance converged, DCDL_NOT_CONVERGED if
  * some hit a cap (their z holds the iterate).  For callers that hold many
  * small or medium solves at once: batching fills the chip where one solve at
@@ -238,6 +244,36 @@ typedef struct {
 int dicodile_csc_batch(int32_t n, const dcdl_shape *shapes, const void *const *X, const void *D,
                        const dcdl_csc_opts *opts, void *const *z_out, dcdl_csc_info *infos,
                        const dcdl_batch_opts *bopts, dcdl_batch_info *binfo, void *stream);
+
+/* Filled by dicodile_csc_batch_autotune when not NULL (host memory). */
+typedef struct {
+  int32_t n_trials;     /* candidate configurations timed */
+  int32_t n_sample;     /* instances in the timing sample */
+  double t_tune_s;      /* wall time of the call */
+  double trial_budget_s;/* round-launch time budget of one trial */
+  double obj_default;   /* summed FP64 objective of the sample after one trial budget with tile
+                           2 L, 256 threads and every co-resident workgroup */
+  double obj_best;      /* ... with the chosen configuration (<= obj_default) */
+  int32_t cached;       /* 1: answered from the per-process cache, nothing timed */
+  int32_t reserved;
+} dcdl_tune_info;
+
+/* Autotuner of dicodile_csc_batch.  Runs candidate configurations on a
+ * sample of up to 12 instances spread over the batch's size range, with the
+ * worker budget scaled to the sample's share of the area (so that every
+ * sampled instance gets the worker grid it gets in the whole batch), each for
+ * the same short time budget, and keeps the one whose sample reaches the
+ * lowest summed FP64 objective (the most progress in equal time):
+ * sub-domain tiles of 1.5, 2, 3 and 4 L_i, then 128 vs 256 threads per
+ * worker, then the whole vs half the co-resident budget (fewer, larger
+ * workers per instance).  Writes the winner into *best (the other fields of
+ * *base are kept; base may be NULL).  Arguments as dicodile_csc_batch, without
+ * outputs: the sample's solutions go to a library workspace.  Results are
+ * cached for the process per (ndim, P, K, L, dtype, mean size class, count
+ * class); a cached answer times nothing. */
+int dicodile_csc_batch_autotune(int32_t n, const dcdl_shape *shapes, const void *const *X, const void *D,
+                                const dcdl_csc_opts *opts, const dcdl_batch_opts *base,
+                                dcdl_batch_opts *best, dcdl_tune_info *info, void *stream);
 
 /* ------------------------------------------------------------------ serving
  * A server solves a stream of eq. csc requests that share one dictionary,

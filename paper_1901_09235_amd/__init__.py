@@ -18,7 +18,7 @@ import os
 
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
            "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
-           "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch", "dicodile_release",
+           "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch_autotune", "dicodile_csc_batch", "dicodile_release",
            "Server", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -67,7 +67,7 @@ class CscInfo(ctypes.Structure):
                 ("n_visits", ctypes.c_int64), ("n_checked", ctypes.c_int64),
                 ("n_patched", ctypes.c_int64), ("t_worker_wait_s", ctypes.c_double),
                 ("t_worker_select_s", ctypes.c_double), ("t_worker_collect_s", ctypes.c_double),
-                ("t_worker_apply_s", ctypes.c_double)]
+                ("t_worker_apply_s", ctypes.c_double), ("beta_drift", ctypes.c_double)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -114,6 +114,8 @@ def load():
     lib.dicodile_csc_batch.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_void_p, vp]
+    lib.dicodile_csc_batch_autotune.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
+                                                ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, vp]
     lib.dicodile_server_create.argtypes = [sp, i32, vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     lib.dicodile_server_submit.argtypes = [vp, sp, vp, ctypes.POINTER(CscOpts), vp,
                                            ctypes.POINTER(ctypes.c_uint64)]
@@ -122,7 +124,7 @@ def load():
     lib.dicodile_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.dicodile_server_destroy.argtypes = [vp]
     for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt", "dicodile_corr",
-              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch",
+              "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch_autotune", "dicodile_csc_batch",
               "dicodile_server_create", "dicodile_server_submit", "dicodile_server_poll",
               "dicodile_server_wait", "dicodile_server_stats", "dicodile_server_destroy"):
         getattr(lib, f).restype = ctypes.c_int
@@ -377,6 +379,47 @@ class BatchInfo(ctypes.Structure):
                 ("n_updates", ctypes.c_int64), ("workers", ctypes.c_int64),
                 ("n_converged", ctypes.c_int32), ("n_passes", ctypes.c_int32),
                 ("used_graph", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class TuneInfo(ctypes.Structure):
+    _fields_ = [("n_trials", ctypes.c_int32), ("n_sample", ctypes.c_int32), ("t_tune_s", ctypes.c_double),
+                ("trial_budget_s", ctypes.c_double), ("obj_default", ctypes.c_double),
+                ("obj_best", ctypes.c_double), ("cached", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _batch_args(Xs, D, lams, tols, opts):
+    n = len(Xs)
+    _device_tensor(D, "D")
+    code = _dtype_code(D)
+    shapes = (Shape * n)()
+    xp = (ctypes.c_void_p * n)()
+    ol = (CscOpts * n)()
+    for i, X in enumerate(Xs):
+        _device_tensor(X, f"X[{i}]")
+        if X.dtype != D.dtype:
+            raise DicodileError(-1, "every X must share D's dtype")
+        shapes[i] = _shape(X, D)
+        xp[i] = X.data_ptr()
+        ol[i] = make_opts(lams[i], tols[i], code, **opts)
+    return shapes, xp, ol
+
+
+def dicodile_csc_batch_autotune(Xs, D, lams, tols, stream=None, **opts):
+    """Tile, threads and worker budget for dicodile_csc_batch, timed on a
+    sample of the batch.  Returns (dict of batch keyword options, info dict)."""
+    lib = load()
+    n = len(Xs)
+    shapes, xp, ol = _batch_args(Xs, D, lams, tols, opts)
+    best = BatchOpts()
+    ti = TuneInfo()
+    rc = lib.dicodile_csc_batch_autotune(ctypes.c_int32(n), ctypes.cast(shapes, ctypes.c_void_p),
+                                         ctypes.cast(xp, ctypes.c_void_p), ctypes.c_void_p(D.data_ptr()),
+                                         ctypes.cast(ol, ctypes.c_void_p), None,
+                                         ctypes.cast(ctypes.byref(best), ctypes.c_void_p),
+                                         ctypes.cast(ctypes.byref(ti), ctypes.c_void_p), _stream(stream))
+    _check(rc)
+    kw = {"workers": best.workers, "threads": best.threads, "tile": (best.tile[0], best.tile[1])}
+    return kw, {f: getattr(ti, f) for f, _ in TuneInfo._fields_ if f != "reserved"}
 
 
 def dicodile_csc_batch(Xs, D, lams, tols, z_outs=None, stream=None, graph=True, workers=0,

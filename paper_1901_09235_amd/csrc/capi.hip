@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <string>
@@ -277,14 +278,15 @@ int residual64_async(hipStream_t stream, const Geom &g, const R *X, const double
 // residual in the "res64" slot and D in FP64 in the "D64" slot.
 template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
-            int positive, double *obj, double *kkt, long long *nnz) {
+            int positive, double *obj, double *kkt, long long *nnz, const R *beta_cmp = nullptr,
+            const double *nrm64 = nullptr, double *drift = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
   WS("res64", sizeof(double) * nx, res);
   WS("scal", 64, scal);
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
-  HIPCK(hipMemsetAsync(scal, 0, 32, stream));
+  HIPCK(hipMemsetAsync(scal, 0, 40, stream));
   int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2);
   if (rc) return rc;
   hipLaunchKernelGGL(sum_squares, dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res, scal);
@@ -293,16 +295,20 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.lambda = lambda;
   o.positive = positive;
   o.result = scal + 1;
+  o.beta_cmp = beta_cmp;
+  o.nrm = nrm64;
+  o.result2 = scal + 4;
   void *pk64;
   if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
   rc = corr64<R, CORR_KKT>(stream, g, res, D64, pk64, o);
   if (rc) return rc;
-  double h[4];
-  HIPCK(hipMemcpyAsync(h, scal, 32, hipMemcpyDeviceToHost, stream));
+  double h[5];
+  HIPCK(hipMemcpyAsync(h, scal, 40, hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
   if (obj) *obj = 0.5 * h[0] + lambda * h[2];
   if (kkt) *kkt = h[1] / lambda;
   if (nnz) *nnz = (long long)h[3];
+  if (drift) *drift = beta_cmp ? h[4] / lambda : std::nan("");
   return DCDL_OK;
 }
 
@@ -331,6 +337,47 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   int rc = pack64<R>(ds, stream, g, D, &pk64);
   if (rc) return rc;
   return corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
+}
+
+// beta = corr(X - Z*D, D) + n z with the residual formed in FP64 and the
+// contraction at the initialisation precision `want` (the periodic refresh of
+// the precision pattern).  FP64 precision, and FP64 data, take the FP64
+// definition (beta_from_z64).
+template <class R>
+int beta_refresh(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
+                 const double *nrm64, R *beta, int want) {
+  const int prec = resolve_prec(want, std::is_same<R, float>::value, g);
+  if constexpr (std::is_same<R, float>::value) {
+    if (prec != DCDL_CORR_F64 && prec >= 0) {
+      const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
+      double *D64, *res, *scal;
+      float *res32;
+      WS("D64", sizeof(double) * nd, D64);
+      WS("res64", sizeof(double) * nx, res);
+      WS("scal", 64, scal);
+      WS("res32", sizeof(float) * nx, res32);
+      hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D,
+                         D64);
+      HIPCK(hipMemsetAsync(scal, 0, 40, stream));
+      int rc = residual64_async<float>(stream, g, X, D64, zpm, res, scal + 2);
+      if (rc) return rc;
+      hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res,
+                         res32);
+      CorrOut ob{};
+      ob.beta = beta;
+      ob.zpm = zpm;
+      ob.nrm = nrm64;
+      void *pk = nullptr;
+      if (prec != DCDL_CORR_DIRECT) {
+        const int mp = mf_of(prec);
+        const MfPlan pl = mf_plan(g, mp);
+        WS("dpk_init", mf_pack_bytes(g, pl, mp), pk);
+        if ((rc = mf_pack<float>(stream, g, pl, mp, D, pk))) return rc;
+      }
+      return corr_beta_at<float>(stream, g, prec, res32, D, pk, ob);
+    }
+  }
+  return beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true);
 }
 
 // Exact FP64 norms from D.
@@ -534,7 +581,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   unsigned long long upd = 0, cands = 0, locked = 0, visits = 0, checked = 0, patched = 0;
   double tw_wait = 0, tw_sel = 0, tw_col = 0, tw_app = 0;
   long long rounds = 0, sweeps = 0;
-  int passes = 0, status = DCDL_NOT_CONVERGED, converged = 0;
+  int passes = 0, n_checks = 0, status = DCDL_NOT_CONVERGED, converged = 0;
+  double beta_drift = std::nan("");
   const long long timeout_ticks = 500000000ll;  // 5 s per neighbour wait, 100 MHz clock
   for (;;) {
     ++passes;
@@ -585,17 +633,29 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     const bool time_capped = hc.status == 4;
     const double tc0 = now_s();
     const bool sweep_done = hc.converged != 0;
-    // FP64 check of the iterate (objective, strict KKT)
-    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz);
+    const bool out_of_time = time_capped || (o->timeout_s > 0 && now_s() - t_start > o->timeout_s);
+    if (!sweep_done && rounds_left > 0 && !out_of_time) {
+      // a refresh chunk ended: beta rebuilt from z by the initialisation
+      // contraction (the refresh of the precision pattern), no check
+      if ((rc = beta_refresh<R>(ds, stream, g, X, D, zpm, nrm64, beta, o->beta_prec))) return rc;
+      hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam,
+                         tol, o->positive, o->certify, score, meta);
+      HIPCK(hipStreamSynchronize(stream));
+      t_check += now_s() - tc0;
+      continue;
+    }
+    // FP64 check of the iterate (objective, strict KKT, drift of the maintained beta)
+    double drift_now = 0;
+    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now);
     if (rc) return rc;
+    if (n_checks++ == 0) beta_drift = drift_now;
     if (sweep_done && kkt <= kkt_target) {
       t_check += now_s() - tc0;
       converged = 1;
       status = DCDL_OK;
       break;
     }
-    if (rounds_left <= 0 || time_capped || (o->timeout_s > 0 && now_s() - t_start > o->timeout_s) ||
-        (sweep_done && passes >= 1 + max_polish)) {
+    if (rounds_left <= 0 || out_of_time || (sweep_done && n_checks >= 1 + max_polish)) {
       t_check += now_s() - tc0;
       break;
     }
@@ -640,6 +700,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     info->t_worker_select_s = tw_sel;
     info->t_worker_collect_s = tw_col;
     info->t_worker_apply_s = tw_app;
+    info->beta_drift = beta_drift;
   }
   return status;
 }
@@ -933,4 +994,5 @@ extern "C" int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, co
   return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
 }
 #include "batch.inc"
+#include "tune.inc"
 #include "serve.inc"

@@ -100,6 +100,8 @@ struct CorrOut {
   double lambda;       // CORR_KKT
   int positive;        // CORR_KKT / CORR_ABSMAX
   double *result;      // CORR_KKT: max violation; CORR_ABSMAX: max |G| (one-sided if positive)
+  const void *beta_cmp;  // CORR_KKT, optional: a maintained beta (H, W, KS) in Rz compared with
+  double *result2;       //   G + n z (needs nrm); result2 receives the max absolute difference
 };
 
 template <class Rin, class Racc, class Rz, int MODE, int KC, int TH>
@@ -114,7 +116,7 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
   const bool valid = h < g.H && w < g.W;
   const long long plane = (long long)g.T1 * g.T2;
   const long long pos = (long long)h * g.W + w;
-  double red = 0.0;
+  double red = 0.0, red2 = 0.0;
   for (int kb = 0; kb < g.K; kb += KC) {
     const int kc = min(KC, g.K - kb);
     Racc acc[KC];
@@ -156,6 +158,8 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
           else
             v = fabs(gv - (z > 0.0 ? o.lambda : -o.lambda));
           red = fmax(red, v);
+          if (o.beta_cmp)
+            red2 = fmax(red2, fabs(gv + o.nrm[k] * z - (double)reinterpret_cast<const Rz *>(o.beta_cmp)[pos * g.KS + k]));
         } else {
           const double gv = (double)acc[q];
           red = fmax(red, o.positive ? gv : fabs(gv));
@@ -168,6 +172,11 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
   if (MODE != CORR_BETA) {
     red = block_max<256>(red, sh_red);
     if (threadIdx.x == 0) atomic_max_nonneg(o.result, fmax(red, 0.0));
+    if (MODE == CORR_KKT && o.beta_cmp) {
+      __syncthreads();
+      red2 = block_max<256>(red2, sh_red);
+      if (threadIdx.x == 0) atomic_max_nonneg(o.result2, red2);
+    }
   }
 }
 
@@ -221,58 +230,12 @@ __global__ __launch_bounds__(256) void convert_kernel(long long n, const Rs *__r
     dst[i] = (Rd)src[i];
 }
 
-// --------------------------------------------------------- sparse residual
+// ------------------------------------------------ non-zero entries and sums
 struct NzEntry {
   int pos;
   int k;
   double z;
 };
-
-// Counts (list == nullptr) or lists the non-zeros of a position-major z of
-// atom stride KS, and accumulates sum |z| in FP64.
-template <class R>
-__global__ __launch_bounds__(256) void collect_nonzeros(long long n, int KS, const R *__restrict__ z,
-                                                        unsigned long long *count, NzEntry *list,
-                                                        unsigned long long cap, double *l1) {
-  __shared__ double sh[4];
-  double a = 0.0;
-  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const R v = z[i];
-    if (v != R(0)) {
-      a += fabs((double)v);
-      const unsigned long long slot = atomicAdd(count, 1ull);
-      if (list && slot < cap) {
-        NzEntry e;
-        e.pos = (int)(i / KS);
-        e.k = (int)(i - (i / KS) * KS);
-        e.z = (double)v;
-        list[slot] = e;
-      }
-    }
-  }
-  if (l1) {
-    a = block_sum<256>(a, sh);
-    if (threadIdx.x == 0) atomic_add_f64(l1, a);
-  }
-}
-
-// res -= z * D_k shifted to pos, for every listed non-zero (eq. model).
-template <class Rd>
-__global__ __launch_bounds__(256) void scatter_atoms(Geom g, const NzEntry *__restrict__ list, long long nnz,
-                                                     const Rd *__restrict__ D, double *__restrict__ res) {
-  const int PL = g.P * g.L1 * g.L2;
-  const long long plane = (long long)g.T1 * g.T2;
-  for (long long e = blockIdx.x; e < nnz; e += gridDim.x) {
-    const NzEntry nz = list[e];
-    const int h = nz.pos / g.W, w = nz.pos - (nz.pos / g.W) * g.W;
-    const Rd *dk = D + (long long)nz.k * PL;
-    for (int i = threadIdx.x; i < PL; i += blockDim.x) {
-      const int p = i / (g.L1 * g.L2), r = i - p * (g.L1 * g.L2);
-      const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
-      atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -nz.z * (double)dk[i]);
-    }
-  }
-}
 
 __global__ __launch_bounds__(256) void sum_squares(long long n, const double *__restrict__ x, double *out) {
   __shared__ double sh[4];

@@ -57,7 +57,7 @@ template <> struct MfT<MF_BF16X3> {
 
 // Layout of the packed dictionary and of the reduction.
 struct MfPlan {
-  int PC;    // channels per chunk (1, 2, 4 or 8)
+  int PC;    // channels per chunk (FP64: 1 ... 8; BF16: 1, 2, 4 or 8)
   int NPC;   // channel chunks
   int L2p;   // t2 extent padded so that L2p * PC is a multiple of the instruction's reduction
   int SPS;   // instruction steps per (t1, chunk) stage = L2p * PC / KK
@@ -231,7 +231,7 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
   // epilogue: register v of a lane holds position column (lane % 16) and, in
   // the 16-atom tile, row (lane / 16) + 4 v for the FP64 instruction and row
   // 4 (lane / 16) + v for the BF16 one
-  double red = 0.0;
+  double red = 0.0, red2 = 0.0;
   const int hh = h0 + wr;
 #pragma unroll
   for (int n = 0; n < NTW; ++n) {
@@ -261,6 +261,9 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
             else
               vv = fabs(gv - (z > 0.0 ? o.lambda : -o.lambda));
             red = fmax(red, vv);
+            if (o.beta_cmp)
+              red2 = fmax(red2, fabs(gv + o.nrm[k] * z -
+                                     (double)reinterpret_cast<const Rz *>(o.beta_cmp)[pos * g.KS + k]));
           } else {
             red = fmax(red, o.positive ? gv : fabs(gv));
           }
@@ -270,6 +273,11 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
   if (MODE != CORR_BETA) {
     red = block_max<256>(red, sh_red);
     if (tid == 0) atomic_max_nonneg(o.result, fmax(red, 0.0));
+    if (MODE == CORR_KKT && o.beta_cmp) {
+      __syncthreads();
+      red2 = block_max<256>(red2, sh_red);
+      if (tid == 0) atomic_max_nonneg(o.result2, red2);
+    }
   }
 }
 

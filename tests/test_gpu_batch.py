@@ -103,3 +103,30 @@ def test_batch_rejects_mismatched_atoms(lib):
     X1 = dev(np.zeros((2,) + pbs[1].X.shape[1:]), torch.float32)  # P differs
     with pytest.raises(lib.DicodileError):
         lib.dicodile_csc_batch([X0, X1], dev(D, torch.float32), [1.0, 1.0], [1e-5, 1e-5])
+
+
+def test_autotuned_batch_matches_oracle_and_is_cached(lib):
+    """The autotuner returns a configuration from its candidate set, answers a
+    second identical request from its cache, and the batch solved with the
+    tuned configuration still meets the oracle's objective and KKT."""
+    D, pbs = _batch(4, n=8, lo=40, hi=120)
+    lams = [0.1 * oracle.lambda_max(pb.X, D) for pb in pbs]
+    Xs = [dev(pb.X, torch.float32) for pb in pbs]
+    Dd = dev(D, torch.float32)
+    tols = [1e-5 * l for l in lams]
+    kw, info = lib.dicodile_csc_batch_autotune(Xs, Dd, lams, tols)
+    assert info["cached"] == 0 and info["n_trials"] == 6 and 1 <= info["n_sample"] <= 8
+    assert info["obj_best"] <= info["obj_default"]
+    assert kw["threads"] in (128, 256)
+    assert kw["tile"][0] in (9, 12, 18, 24) and kw["tile"][1] in (9, 12, 18, 24)
+    kw2, info2 = lib.dicodile_csc_batch_autotune(Xs, Dd, lams, tols)
+    assert info2["cached"] == 1 and kw2 == kw
+    zs, infos, binfo = lib.dicodile_csc_batch(Xs, Dd, lams, tols, **kw)
+    assert binfo["n_converged"] == len(pbs)
+    for pb, lam, z in zip(pbs, lams, zs):
+        X = pb.X.astype(np.float32).astype(np.float64)
+        Dd64 = D.astype(np.float32).astype(np.float64)
+        Zo, _ = oracle.lgcd(X, Dd64, lam, 1e-10 * lam)
+        fo = oracle.objective(X, Dd64, Zo, lam)
+        fg = oracle.objective(X, Dd64, z.double().cpu().numpy(), lam)
+        assert (fg - fo) / fo <= 1e-6
