@@ -228,9 +228,10 @@ def run_serving(args):
     n_warm, n_meas = args.serve_warmup, args.requests
     arrivals = synth.serving_arrivals(n_warm + n_meas, rate_hz=args.rate)
     which = [i % len(pool) for i in range(n_warm + n_meas)]
-    # one output per in-flight request: a ring deep enough for any backlog here
-    ring = min(len(which), 512)
-    zs = [torch.empty((D.shape[0], Xs[which[i]].shape[1] - L + 1), dtype=torch.float32, device="cuda")
+    # one output per in-flight request: a ring deep enough for any backlog here,
+    # a multiple of the pool so that slot i % ring always holds signal i % pool
+    ring = len(pool) * max(1, 512 // len(pool))
+    zs = [torch.empty((D.shape[0], Xs[i % len(pool)].shape[1] - L + 1), dtype=torch.float32, device="cuda")
           for i in range(ring)]
     torch.cuda.synchronize()
     max_len = max(X.shape[1] for X in Xs)
@@ -253,7 +254,7 @@ def run_serving(args):
                 ready.acquire()
                 results[i] = srv.wait(tickets[i])[1]
         try:
-            th = threading.Thread(target=collect)
+            th = threading.Thread(target=collect, daemon=True)
             th.start()
             start = time.monotonic() + 0.05
             for i in range(n):

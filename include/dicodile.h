@@ -96,14 +96,14 @@ typedef struct {
   int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
   int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library */
   int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
-  int32_t refresh_every;  /* rebuild beta from z every this many sweeps of rounds by the
-                             beta_prec contraction over the FP64 residual (the periodic refresh);
-                             0 -> never.  FP64 drift correction runs after a failed final check */
+  int32_t refresh_every;  /* rebuild beta from its FP64 definition every this many sweeps of rounds
+                             (periodic drift correction); 0 -> only after a failed final check */
   int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
   int32_t inner;          /* sub-domain visits per worker per round; 0 -> 1 */
   int32_t beta_prec;      /* dcdl_corr_prec of the contraction that initialises beta from X
-                             (0 -> FP32: BF16X3 matrix cores; FP64: FP64 matrix cores).  The
-                             drift correction and the final check are FP64 whatever this is */
+                             (0 -> FP32: BF16X3 matrix cores; FP64: FP64 matrix cores).  Every
+                             later recomputation (periodic or after a failed check) and the final
+                             check are FP64 whatever this is */
   int64_t max_rounds;     /* cap on worker rounds (0 -> unlimited) */
   double div_guard;       /* stop with DCDL_EDIVERGED if |Z| exceeds this (0 -> off) */
   double timeout_s;       /* wall-clock cap for the whole call (0 -> none) */
@@ -201,6 +201,79 @@ int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void
  * Accumulation is in FP64 over the non-zeros of z. */
 int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, const void *z, const void *X,
                         void *ztz_out, void *ztX_out, void *stream);
+
+/* ------------------------------------------------------- dictionary update */
+
+/* Options of dicodile_dict_update.  Zero-initialise for defaults. */
+typedef struct {
+  int32_t max_iter;   /* projected-gradient iterations at most; 0 -> 500 */
+  int32_t reserved;
+  double tol;         /* stop when an iteration decreases F by less than tol * max(1, F); 0 -> 1e-10 */
+  double c1;          /* Armijo sufficient-decrease constant in (0, 1); 0 -> 1e-4 */
+} dcdl_dict_opts;
+
+/* Filled by dicodile_dict_update when not NULL (host memory). */
+typedef struct {
+  int32_t iterations;   /* accepted projected-gradient steps */
+  int32_t backtracks;   /* halvings of the step over all iterations */
+  double cost_initial;  /* F(D) = 1/2 ||X - Z*D||^2 at the projected input D */
+  double cost;          /* F at the returned D */
+  double t_s;           /* wall time of the call */
+} dcdl_dict_info;
+
+/* Dictionary update of eq. dict_update (Sec. 4.2):
+ *   D = argmin_{||D_k||_2 <= 1} 1/2 ||X - Z*D||^2
+ * from the sufficient statistics of eq. phi alone (no signal-size work):
+ *   F(D) = 1/2 ||X||^2 - <D, ztX> + 1/2 <D, Q(D)>,  grad F = Q(D) - ztX,
+ *   Q(D)_{k,p}[t] = sum_{k'} sum_{t'} ztz[k][k'][t - t' + L - 1] D_{k',p}[t'].
+ * Projected gradient descent with an Armijo backtracking line search along the
+ * projection arc (the paper's PGD + Armijo): the trial D(a) = Proj(D - a grad F)
+ * is accepted when F(D(a)) <= F(D) + c1 <grad F(D), D(a) - D>; a starts at twice
+ * the last accepted step (the first at 1 / max_k sum_{k', tau} |ztz[k][k'][tau]|,
+ * an upper bound of the largest eigenvalue of the quadratic form) and halves on
+ * rejection.  Proj scales atoms of norm above 1 back to the unit sphere.
+ * dict_shape: ndim, P, K, L of D (T is ignored).  ztz (K, K, 2L-1 ...) and
+ * ztX (K, P, L ...): device, dtype, as dicodile_dict_stats writes them.
+ * x_sq: ||X||^2 (host; it only shifts the reported costs).  D_inout: (K, P, L ...)
+ * device, dtype: the start on entry, the result on return.  All arithmetic is
+ * FP64.  Needs |Theta| <= 2048 taps. */
+int dicodile_dict_update(const dcdl_shape *dict_shape, dcdl_dtype dtype, const void *ztz, const void *ztX,
+                         double x_sq, void *D_inout, const dcdl_dict_opts *opts, dcdl_dict_info *info,
+                         void *stream);
+
+/* Options of dicodile_cdl.  Zero-initialise for defaults. */
+typedef struct {
+  double lambda_frac;     /* lambda = lambda_frac * lambda_max(X, D_start), fixed for the run; 0 -> 0.1 */
+  double nu;              /* stop when an outer iteration lowers the objective by less than nu times
+                             its previous value; 0 -> 1e-4 */
+  int32_t max_outer;      /* outer iterations at most; 0 -> 20 (at most 64) */
+  int32_t no_warm_start;  /* 1: every CSC step starts from Z = 0 (default: from the previous Z) */
+  double tol_rel;         /* CSC tolerance in units of lambda; 0 -> 1e-5 */
+  dcdl_csc_opts csc;      /* the CSC step's other options (lambda, tol, dtype, warm_start are set here) */
+  dcdl_dict_opts dict;    /* the dictionary update's options */
+} dcdl_cdl_opts;
+
+/* Filled by dicodile_cdl when not NULL (host memory). */
+typedef struct {
+  int32_t outer;             /* outer iterations run */
+  int32_t converged;         /* 1: stopped by nu */
+  double lambda;             /* the lambda used */
+  double objective[64];      /* 1/2 ||X - Z*D||^2 + lambda ||Z||_1 after each dictionary update */
+  double objective_z[64];    /* ... after each CSC step (FP64 check) */
+  double t_total_s, t_csc_s, t_stats_s, t_dict_s;
+  int64_t n_updates;         /* coordinate updates over all CSC steps */
+} dcdl_cdl_info;
+
+/* Convolutional dictionary learning, Alg. 2: alternate the CSC step
+ * (dicodile_csc with lambda fixed as above; warm-started from the previous Z),
+ * the statistics of eq. phi and the dictionary update, until the relative
+ * decrease of the objective over one outer iteration is below nu.
+ * X: (P, T ...) device, dtype.  D_inout: (K, P, L ...) device, dtype: the start
+ * (projected onto the feasible set) on entry, the learned dictionary on return.
+ * z_out: (K, T-L+1 ...) device, dtype: the last CSC step's Z.  Returns DCDL_OK
+ * when stopped by nu, DCDL_NOT_CONVERGED at max_outer. */
+int dicodile_cdl(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, void *D_inout, void *z_out,
+                 const dcdl_cdl_opts *opts, dcdl_cdl_info *info, void *stream);
 
 /* Batch-level options of dicodile_csc_batch.  Zero-initialise for defaults. */
 typedef struct {

@@ -19,7 +19,7 @@ import os
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
            "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
            "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch_autotune", "dicodile_csc_batch", "dicodile_release",
-           "Server", "STATUS"]
+           "dicodile_dict_update", "dicodile_cdl", "Server", "STATUS"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "_build", "libdicodile_mi355x.so")
@@ -85,6 +85,29 @@ class ServerStats(ctypes.Structure):
                 ("t_rounds_s", ctypes.c_double), ("t_busy_s", ctypes.c_double)]
 
 
+class DictOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("reserved", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("c1", ctypes.c_double)]
+
+
+class DictInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("backtracks", ctypes.c_int32),
+                ("cost_initial", ctypes.c_double), ("cost", ctypes.c_double), ("t_s", ctypes.c_double)]
+
+
+class CdlOpts(ctypes.Structure):
+    _fields_ = [("lambda_frac", ctypes.c_double), ("nu", ctypes.c_double), ("max_outer", ctypes.c_int32),
+                ("no_warm_start", ctypes.c_int32), ("tol_rel", ctypes.c_double), ("csc", CscOpts),
+                ("dict", DictOpts)]
+
+
+class CdlInfo(ctypes.Structure):
+    _fields_ = [("outer", ctypes.c_int32), ("converged", ctypes.c_int32), ("lambda_", ctypes.c_double),
+                ("objective", ctypes.c_double * 64), ("objective_z", ctypes.c_double * 64),
+                ("t_total_s", ctypes.c_double), ("t_csc_s", ctypes.c_double), ("t_stats_s", ctypes.c_double),
+                ("t_dict_s", ctypes.c_double), ("n_updates", ctypes.c_int64)]
+
+
 def library_path() -> str:
     return _LIB_PATH
 
@@ -116,6 +139,9 @@ def load():
                                        ctypes.c_void_p, vp]
     lib.dicodile_csc_batch_autotune.argtypes = [i32, ctypes.c_void_p, ctypes.c_void_p, vp, ctypes.c_void_p,
                                                 ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, vp]
+    lib.dicodile_dict_update.argtypes = [sp, i32, vp, vp, dbl, vp, ctypes.POINTER(DictOpts),
+                                         ctypes.POINTER(DictInfo), vp]
+    lib.dicodile_cdl.argtypes = [sp, i32, vp, vp, vp, ctypes.POINTER(CdlOpts), ctypes.POINTER(CdlInfo), vp]
     lib.dicodile_server_create.argtypes = [sp, i32, vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
     lib.dicodile_server_submit.argtypes = [vp, sp, vp, ctypes.POINTER(CscOpts), vp,
                                            ctypes.POINTER(ctypes.c_uint64)]
@@ -350,6 +376,69 @@ def dicodile_dict_stats(z, X, L, stream=None):
                                    ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(ztz.data_ptr()),
                                    ctypes.c_void_p(ztX.data_ptr()), _stream(stream)))
     return ztz, ztX
+
+
+def _dict_shape(D) -> Shape:
+    s = Shape()
+    if D.dim() == 3:
+        s.ndim, s.P, s.K, s.L[0], s.T[0] = 1, D.shape[1], D.shape[0], D.shape[2], D.shape[2]
+    elif D.dim() == 4:
+        s.ndim, s.P, s.K = 2, D.shape[1], D.shape[0]
+        s.L[0], s.L[1], s.T[0], s.T[1] = D.shape[2], D.shape[3], D.shape[2], D.shape[3]
+    else:
+        raise DicodileError(-1, f"unsupported dictionary shape {tuple(D.shape)}")
+    return s
+
+
+def dicodile_dict_update(ztz, ztX, x_sq: float, D, max_iter: int = 0, tol: float = 0.0, c1: float = 0.0,
+                         stream=None) -> dict:
+    """Dictionary update of eq. dict_update from the statistics (ztz, ztX);
+    D is updated in place.  Returns the info dict."""
+    lib = load()
+    for t, n in ((ztz, "ztz"), (ztX, "ztX"), (D, "D")):
+        _device_tensor(t, n)
+        if t.dtype != D.dtype:
+            raise DicodileError(-1, "ztz, ztX and D must share a dtype")
+    o = DictOpts()
+    o.max_iter, o.tol, o.c1 = int(max_iter), float(tol), float(c1)
+    info = DictInfo()
+    _check(lib.dicodile_dict_update(ctypes.byref(_dict_shape(D)), _dtype_code(D), ctypes.c_void_p(ztz.data_ptr()),
+                                    ctypes.c_void_p(ztX.data_ptr()), float(x_sq), ctypes.c_void_p(D.data_ptr()),
+                                    ctypes.byref(o), ctypes.byref(info), _stream(stream)))
+    return {f: getattr(info, f) for f, _ in DictInfo._fields_}
+
+
+def dicodile_cdl(X, D, lambda_frac: float = 0.1, nu: float = 1e-4, max_outer: int = 0, tol_rel: float = 0.0,
+                 warm_start: bool = True, z_out=None, dict_max_iter: int = 0, dict_tol: float = 0.0, stream=None,
+                 **csc_opts):
+    """Alg. 2 (convolutional dictionary learning): D is updated in place.
+    Returns (z, info dict with the objective after each outer iteration)."""
+    torch = _torch()
+    lib = load()
+    _device_tensor(X, "X")
+    _device_tensor(D, "D")
+    if X.dtype != D.dtype:
+        raise DicodileError(-1, "X and D must share a dtype")
+    s = _shape(X, D)
+    if z_out is None:
+        z_out = torch.empty(_zshape(s), dtype=X.dtype, device=X.device)
+    _device_tensor(z_out, "z_out")
+    o = CdlOpts()
+    o.lambda_frac, o.nu, o.max_outer, o.tol_rel = float(lambda_frac), float(nu), int(max_outer), float(tol_rel)
+    o.no_warm_start = int(not warm_start)
+    o.csc = make_opts(1.0, 0.0, _dtype_code(X), **csc_opts)
+    o.dict.max_iter, o.dict.tol = int(dict_max_iter), float(dict_tol)
+    info = CdlInfo()
+    rc = lib.dicodile_cdl(ctypes.byref(s), _dtype_code(X), ctypes.c_void_p(X.data_ptr()),
+                          ctypes.c_void_p(D.data_ptr()), ctypes.c_void_p(z_out.data_ptr()), ctypes.byref(o),
+                          ctypes.byref(info), _stream(stream))
+    _check(rc, allow_not_converged=True)
+    n = info.outer
+    d = {"outer": n, "converged": info.converged, "lambda": info.lambda_,
+         "objective": list(info.objective[:n]), "objective_z": list(info.objective_z[:n]),
+         "t_total_s": info.t_total_s, "t_csc_s": info.t_csc_s, "t_stats_s": info.t_stats_s,
+         "t_dict_s": info.t_dict_s, "n_updates": info.n_updates, "status": STATUS.get(rc, rc)}
+    return z_out, d
 
 
 def dicodile_copy_probe(dst, src, repeats: int = 10, stream=None) -> float:

@@ -23,6 +23,7 @@
 #include "dcdl_device.h"
 #include "dcdl_kernels.h"
 #include "dcdl_mfma.h"
+#include "dcdl_dict.h"
 
 using namespace dcdl;
 
@@ -339,47 +340,6 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   return corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
 }
 
-// beta = corr(X - Z*D, D) + n z with the residual formed in FP64 and the
-// contraction at the initialisation precision `want` (the periodic refresh of
-// the precision pattern).  FP64 precision, and FP64 data, take the FP64
-// definition (beta_from_z64).
-template <class R>
-int beta_refresh(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
-                 const double *nrm64, R *beta, int want) {
-  const int prec = resolve_prec(want, std::is_same<R, float>::value, g);
-  if constexpr (std::is_same<R, float>::value) {
-    if (prec != DCDL_CORR_F64 && prec >= 0) {
-      const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
-      double *D64, *res, *scal;
-      float *res32;
-      WS("D64", sizeof(double) * nd, D64);
-      WS("res64", sizeof(double) * nx, res);
-      WS("scal", 64, scal);
-      WS("res32", sizeof(float) * nx, res32);
-      hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D,
-                         D64);
-      HIPCK(hipMemsetAsync(scal, 0, 40, stream));
-      int rc = residual64_async<float>(stream, g, X, D64, zpm, res, scal + 2);
-      if (rc) return rc;
-      hipLaunchKernelGGL((convert_kernel<double, float>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res,
-                         res32);
-      CorrOut ob{};
-      ob.beta = beta;
-      ob.zpm = zpm;
-      ob.nrm = nrm64;
-      void *pk = nullptr;
-      if (prec != DCDL_CORR_DIRECT) {
-        const int mp = mf_of(prec);
-        const MfPlan pl = mf_plan(g, mp);
-        WS("dpk_init", mf_pack_bytes(g, pl, mp), pk);
-        if ((rc = mf_pack<float>(stream, g, pl, mp, D, pk))) return rc;
-      }
-      return corr_beta_at<float>(stream, g, prec, res32, D, pk, ob);
-    }
-  }
-  return beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true);
-}
-
 // Exact FP64 norms from D.
 template <class R>
 __global__ void norms64(int K, int PL, const R *D, double *nrm) {
@@ -635,9 +595,10 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     const bool sweep_done = hc.converged != 0;
     const bool out_of_time = time_capped || (o->timeout_s > 0 && now_s() - t_start > o->timeout_s);
     if (!sweep_done && rounds_left > 0 && !out_of_time) {
-      // a refresh chunk ended: beta rebuilt from z by the initialisation
-      // contraction (the refresh of the precision pattern), no check
-      if ((rc = beta_refresh<R>(ds, stream, g, X, D, zpm, nrm64, beta, o->beta_prec))) return rc;
+      // a refresh chunk ended: beta rebuilt from its FP64 definition, no check.
+      // (A coarser contraction here would re-inject errors above tol at every
+      // chunk, and the sweep certificate could never be reached.)
+      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
       hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam,
                          tol, o->positive, o->certify, score, meta);
       HIPCK(hipStreamSynchronize(stream));
@@ -720,6 +681,30 @@ int corr_impl(DeviceState *ds, hipStream_t stream, Geom g, const R *X, const R *
   return DCDL_OK;
 }
 
+// lambda_max = max |corr(X, D)| (one-sided if positive) in FP64 (Sec. 2).
+template <class R>
+int lambda_max_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, int positive,
+                    double *out) {
+  const long long nx = (long long)g.P * g.T1 * g.T2, nd = (long long)g.K * g.P * g.L1 * g.L2;
+  double *X64, *D64, *scal;
+  WS("res64", sizeof(double) * nx, X64);
+  WS("D64", sizeof(double) * nd, D64);
+  WS("scal", 64, scal);
+  hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, X64);
+  hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
+  HIPCK(hipMemsetAsync(scal, 0, 16, stream));
+  CorrOut o{};
+  o.positive = positive;
+  o.result = scal;
+  void *pk64;
+  int rc = pack64<double>(ds, stream, g, D64, &pk64);
+  if (rc) return rc;
+  if ((rc = corr64<double, CORR_ABSMAX>(stream, g, X64, D64, pk64, o))) return rc;
+  HIPCK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  return DCDL_OK;
+}
+
 struct Guard {
   DeviceState *ds;
   explicit Guard(DeviceState *d) : ds(d) { ds->mu.lock(); }
@@ -794,30 +779,8 @@ int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X
   if (!X || !D || !out) return fail(DCDL_EINVAL, "NULL pointer");
   if (dtype != DCDL_F32 && dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
   PROLOGUE();
-  const long long nx = (long long)g.P * g.T1 * g.T2, nd = (long long)g.K * g.P * g.L1 * g.L2;
-  double *X64, *D64, *scal;
-  WS("res64", sizeof(double) * nx, X64);
-  WS("D64", sizeof(double) * nd, D64);
-  WS("scal", 64, scal);
-  if (dtype == DCDL_F32) {
-    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx,
-                       (const float *)X, X64);
-    hipLaunchKernelGGL((convert_kernel<float, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd,
-                       (const float *)D, D64);
-  } else {
-    HIPCK(hipMemcpyAsync(X64, X, sizeof(double) * nx, hipMemcpyDeviceToDevice, stream));
-    HIPCK(hipMemcpyAsync(D64, D, sizeof(double) * nd, hipMemcpyDeviceToDevice, stream));
-  }
-  HIPCK(hipMemsetAsync(scal, 0, 16, stream));
-  CorrOut o{};
-  o.positive = positive;
-  o.result = scal;
-  void *pk64;
-  if ((rc = pack64<double>(ds, stream, g, D64, &pk64))) return rc;
-  if ((rc = corr64<double, CORR_ABSMAX>(stream, g, X64, D64, pk64, o))) return rc;
-  HIPCK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
-  HIPCK(hipStreamSynchronize(stream));
-  return DCDL_OK;
+  if (dtype == DCDL_F32) return lambda_max_impl<float>(ds, stream, g, (const float *)X, (const float *)D, positive, out);
+  return lambda_max_impl<double>(ds, stream, g, (const double *)X, (const double *)D, positive, out);
 }
 
 int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dcdl_csc_opts *opts, void *z_out,
@@ -914,7 +877,8 @@ int dicodile_copy_probe(void *dst, const void *src, size_t bytes, int32_t repeat
 namespace {
 
 template <class R>
-int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R *z, const R *X, R *ztz, R *ztX) {
+int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R *z, const R *X, R *ztz, R *ztX,
+                    double **phi64_out = nullptr, double **psi64_out = nullptr) {
   const long long HW = (long long)g.H * g.W, nz = HW * g.K;
   const long long nphi = (long long)g.K * g.K * g.U1 * g.U2, npsi = (long long)g.K * g.P * g.L1 * g.L2;
   unsigned int *cnt;
@@ -967,12 +931,16 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
     hipLaunchKernelGGL(phi_kernel<R>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, total, zpm, nzc, phi64);
     HIPCK(hipGetLastError());
   }
-  hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(nphi)), dim3(256), 0, stream, nphi, phi64,
-                     ztz);
-  hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(npsi)), dim3(256), 0, stream, npsi, psi64,
-                     ztX);
+  if (ztz)
+    hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(nphi)), dim3(256), 0, stream, nphi,
+                       phi64, ztz);
+  if (ztX)
+    hipLaunchKernelGGL((convert_kernel<double, R>), dim3(grid_stride_blocks(npsi)), dim3(256), 0, stream, npsi,
+                       psi64, ztX);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
+  if (phi64_out) *phi64_out = phi64;
+  if (psi64_out) *psi64_out = psi64;
   return DCDL_OK;
 }
 
@@ -995,4 +963,5 @@ extern "C" int dicodile_dict_stats(const dcdl_shape *shape, dcdl_dtype dtype, co
 }
 #include "batch.inc"
 #include "tune.inc"
+#include "dict.inc"
 #include "serve.inc"

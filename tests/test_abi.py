@@ -55,6 +55,9 @@ int main(void) {
          offsetof(dcdl_csc_info, t_worker_apply_s));
   printf("%zu %zu %zu %zu\\n", sizeof(dcdl_server_opts), sizeof(dcdl_server_stats),
          offsetof(dcdl_server_opts, tile), offsetof(dcdl_server_stats, t_busy_s));
+  printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dcdl_dict_opts), sizeof(dcdl_dict_info), sizeof(dcdl_cdl_opts),
+         sizeof(dcdl_cdl_info), offsetof(dcdl_cdl_opts, dict), offsetof(dcdl_cdl_info, n_updates));
+  printf("%zu %zu\\n", sizeof(dcdl_tune_info), offsetof(dcdl_csc_info, beta_drift));
   return 0;
 }
 """)
@@ -72,6 +75,11 @@ int main(void) {
     srv = [int(v) for v in lines[3].split()]
     assert srv == [ctypes.sizeof(dl.ServerOpts), ctypes.sizeof(dl.ServerStats), dl.ServerOpts.tile.offset,
                    dl.ServerStats.t_busy_s.offset]
+    dct = [int(v) for v in lines[4].split()]
+    assert dct == [ctypes.sizeof(dl.DictOpts), ctypes.sizeof(dl.DictInfo), ctypes.sizeof(dl.CdlOpts),
+                   ctypes.sizeof(dl.CdlInfo), dl.CdlOpts.dict.offset, dl.CdlInfo.n_updates.offset]
+    last = [int(v) for v in lines[5].split()]
+    assert last == [ctypes.sizeof(dl.TuneInfo), dl.CscInfo.beta_drift.offset]
 
 
 def test_argument_checks_before_device_access(lib):
@@ -98,6 +106,9 @@ def test_argument_checks_before_device_access(lib):
     assert lib.dicodile_server_wait(None, 1, 0.0, None) == -1
     assert lib.dicodile_server_stats(None, None) == -1
     assert lib.dicodile_server_destroy(None) == 0
+    assert lib.dicodile_dict_update(None, 0, None, None, 0.0, None, None, None, None) == -1
+    assert lib.dicodile_cdl(None, 0, None, None, None, None, None, None) == -1
+    assert lib.dicodile_corr(None, 0, None, None, None, 0, None) == -1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

@@ -113,7 +113,7 @@ def test_solve_reaches_oracle_with_each_init_precision(lib, beta_prec):
     Dd = D.astype(np.float32).astype(np.float64)
     lam = 0.1 * oracle.lambda_max(X, Dd)
     z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
-                               beta_prec=beta_prec, max_polish=4)
+                               beta_prec=beta_prec, max_polish=4, timeout_s=60)
     assert info["status"] == "OK", info
     Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
     fo = oracle.objective(X, Dd, Zo, lam)
@@ -134,7 +134,7 @@ def test_beta_drift_is_reported_and_orders_by_precision(lib):
     lam = 0.1 * oracle.lambda_max(pb.X.astype(np.float32).astype(np.float64), D.astype(np.float32).astype(np.float64))
     drift = {}
     for prec in ("f64", "bf16x3", "bf16"):
-        _, info = lib.dicodile_csc(X, Dd, lam, 1e-5 * lam, beta_prec=prec, max_polish=4)
+        _, info = lib.dicodile_csc(X, Dd, lam, 1e-5 * lam, beta_prec=prec, max_polish=4, timeout_s=60)
         assert info["status"] == "OK"
         drift[prec] = info["beta_drift"]
     assert all(np.isfinite(v) and v >= 0 for v in drift.values()), drift
@@ -142,17 +142,18 @@ def test_beta_drift_is_reported_and_orders_by_precision(lib):
     assert drift["f64"] < 1e-3 and drift["bf16x3"] < 1e-2, drift
 
 
-@pytest.mark.parametrize("beta_prec", ["bf16", "bf16x3", "f64"])
-def test_periodic_refresh_at_each_precision_reaches_oracle(lib, beta_prec):
-    """refresh_every rebuilds beta from z by the initialisation contraction
-    during the solve; the result still meets the oracle's objective and KKT."""
+@pytest.mark.parametrize("beta_prec", ["bf16", "f64"])
+def test_periodic_refresh_reaches_oracle(lib, beta_prec):
+    """refresh_every rebuilds beta from its FP64 definition between chunks of
+    rounds (whatever contraction initialised it); the solve still certifies
+    and meets the oracle's objective."""
     D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(11)), 6, 2, 24)
     pb = synth.make_problem("p", 903, P=2, T=5000, K=6, L=24, rho=0.005, amp="uniform", sigma=0.1, D=D)
     X = pb.X.astype(np.float32).astype(np.float64)
     Dd = D.astype(np.float32).astype(np.float64)
     lam = 0.1 * oracle.lambda_max(X, Dd)
     z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
-                               beta_prec=beta_prec, refresh_every=1, grid=4, max_polish=4)
+                               beta_prec=beta_prec, refresh_every=2, grid=4, max_polish=4, timeout_s=60)
     assert info["status"] == "OK", info
     Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
     fo = oracle.objective(X, Dd, Zo, lam)

@@ -62,12 +62,12 @@ def test_each_request_alone_and_in_the_mix(lib, dtype):
     alone = []
     with lib.Server(Dd, max_workers=16, slice_rounds=32, max_len=8192) as srv:
         for X, lam in zip(Xs, lams):
-            t = srv.submit(X, lam, rel * lam)
-            z, info = srv.wait(t)
+            t = srv.submit(X, lam, rel * lam, timeout_s=60)
+            z, info = srv.wait(t, timeout_s=120)
             assert info["status"] == "OK", info
             alone.append((z.clone(), info))
-        tickets = [srv.submit(X, lam, rel * lam) for X, lam in zip(Xs, lams)]
-        mixed = [srv.wait(t) for t in tickets]
+        tickets = [srv.submit(X, lam, rel * lam, timeout_s=60) for X, lam in zip(Xs, lams)]
+        mixed = [srv.wait(t, timeout_s=120) for t in tickets]
         st = srv.stats()
     assert st["n_done"] == 2 * len(pbs) and st["peak_active"] >= 2
     for pb, lam, (za, ia), (zm, im) in zip(pbs, lams, alone, mixed):
@@ -87,8 +87,8 @@ def test_long_request_spans_many_slices(lib):
     Xs = [dev(pb.X, torch.float32) for pb in pbs]
     torch.cuda.synchronize()
     with lib.Server(Dd, max_workers=4, slice_rounds=8, max_len=8192) as srv:
-        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
-        res = [srv.wait(t) for t in tickets]
+        tickets = [srv.submit(X, lam, 1e-5 * lam, timeout_s=60) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t, timeout_s=120) for t in tickets]
         st = srv.stats()
     assert st["n_launches"] > 10
     long_info = res[0][1]
@@ -109,8 +109,8 @@ def test_image_requests(lib):
     with lib.Server(Dd, max_workers=9, slice_rounds=16, max_len=4096) as srv:
         Xs = [dev(pb.X, torch.float32) for pb in pbs]
         torch.cuda.synchronize()
-        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
-        res = [srv.wait(t) for t in tickets]
+        tickets = [srv.submit(X, lam, 1e-5 * lam, timeout_s=60) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t, timeout_s=120) for t in tickets]
     for pb, lam, (z, info) in zip(pbs, lams, res):
         assert info["status"] == "OK"
         _check_against_oracle(pb, D, lam, z, info, torch.float32)
@@ -127,8 +127,8 @@ def test_admission_waits_for_memory(lib):
     # beta + z (2 * 8 * 4 B) + score (4 B) + meta (4 B) per position, rounded up
     one = 2 * 8 * 4 * 2969 + 8 * 2969 + 4 * 256
     with lib.Server(Dd, hbm_budget_bytes=one + one // 2, max_len=4096) as srv:
-        tickets = [srv.submit(X, lam, 1e-5 * lam) for X, lam in zip(Xs, lams)]
-        res = [srv.wait(t) for t in tickets]
+        tickets = [srv.submit(X, lam, 1e-5 * lam, timeout_s=60) for X, lam in zip(Xs, lams)]
+        res = [srv.wait(t, timeout_s=120) for t in tickets]
         st = srv.stats()
     assert st["peak_active"] == 1
     for pb, lam, (z, info) in zip(pbs, lams, res):
@@ -154,8 +154,8 @@ def test_server_errors(lib):
         with pytest.raises(lib.DicodileError):        # unknown ticket
             srv.poll(12345)
         lam = 0.2 * oracle.lambda_max(pbs[0].X, D)
-        t = srv.submit(X, lam, 1e-5 * lam)
-        z, info = srv.wait(t)
+        t = srv.submit(X, lam, 1e-5 * lam, timeout_s=60)
+        z, info = srv.wait(t, timeout_s=120)
         assert info["status"] == "OK"
         with pytest.raises(lib.DicodileError):        # a finished ticket is forgotten
             srv.poll(t)
