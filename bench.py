@@ -314,6 +314,8 @@ def run_serving(args):
             now = time.monotonic()
             plat.append(now - (start + arrivals[i]))
             pdone.append(now)
+            if (i + 1) % 500 == 0:
+                print(f"# plain form: {i + 1} requests", file=sys.stderr, flush=True)
             if j in served_obj:
                 gap = max(gap, abs(info["objective"] - served_obj[j]) / info["objective"])
         pspan = pdone[-1] - (start + arrivals[0])
