@@ -371,6 +371,128 @@ __device__ __forceinline__ void patch_region(const Inst<R> &I, const PatchCtx<R,
   }
 }
 
+// An accepted update as the apply phase uses it: atom k0 at (ch, cw0), change
+// delta, and the rows [r1, r2) x columns [c1, c2) of this worker's region it
+// patches.
+template <class R> struct UCand {
+  int k0, ch, cw0, r1, r2, c1, c2;
+  int aoff;  // element offset in A of (row 0, column 0) for this update: ((k0 U1 - ch + L1 - 1) U2 - cw0 + L2 - 1) KS
+  R delta;
+};
+
+// Applies every update of `uc` to this worker's region in one pass over the
+// bounding box [R1, R2) x [C1, C2) of their patches: each position reads beta
+// once, subtracts the contributions of the updates whose patch covers it
+// (eq. beta_update; the updated coordinate of each update keeps its value from
+// before that update), writes beta once and recomputes its best-move cache
+// once.  Positions no update covers are left untouched.  The sum runs over
+// the updates in increasing worker order, as applying them one after another
+// would.  Every thread of the workgroup takes part.
+template <class R, int NT>
+__device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int nc,
+                                            int R1, int R2, int C1, int C2) {
+  constexpr int LBUF = 4096;
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  const int tid = threadIdx.x;
+  const int K = I.K, KS = I.KS, W = I.W, G = P.G;
+  const int rowstride = I.U2 * KS;
+  const int ncol = C2 - C1;
+  const int cw = min(ncol, LBUF / G);
+  const int rc = max(1, LBUF / (cw * G));
+  for (int rr0 = R1; rr0 < R2; rr0 += rc) {
+    const int rr1 = min(rr0 + rc, R2);
+    for (int cc0 = C1; cc0 < C2; cc0 += cw) {
+      const int ccw = min(cw, C2 - cc0);
+      const int ng = ccw * G;
+      for (int rr = rr0; rr < rr1; ++rr) {
+        R *prow = P.sh_ps + (rr - rr0) * ng;
+        uint16_t *krow = P.sh_pk + (rr - rr0) * ng;
+        unsigned rm = 0;  // updates whose patch covers row rr
+        for (int c = 0; c < nc; ++c)
+          if (rr >= uc[c].r1 && rr < uc[c].r2) rm |= 1u << c;
+        if (!rm) {
+          for (int j = tid; j < ng; j += NT) prow[j] = R(-2);
+          continue;
+        }
+        V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
+        const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
+        const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
+        const int arow = rr * rowstride;
+        int pl = P.pl0, qq = P.q0;
+#pragma unroll 1
+        for (int j = tid; j < ng; j += NT) {
+          const int cc = cc0 + pl;
+          V b = Vec<R>::zero();
+          bool any = false;
+          unsigned m = rm;
+          while (m) {
+            const int c = __ffs(m) - 1;
+            m &= m - 1;
+            const UCand<R> &u = uc[c];
+            if (cc < u.c1 || cc >= u.c2) continue;
+            if (!any) {
+              b = brow[j];
+              any = true;
+            }
+            const V av = *reinterpret_cast<const V *>(I.A + (u.aoff + arow + cc * KS + qq * VE));
+            const V bold = b;
+            b = Vec<R>::fma_neg(b, av, u.delta);
+            if (rr == u.ch && cc == u.cw0 && qq == u.k0 / VE)
+              Vec<R>::set(b, u.k0 % VE, Vec<R>::get(bold, u.k0 % VE));  // the updated coordinate itself
+          }
+          if (any) {
+            brow[j] = b;
+            const uint32_t mt = mrow[pl];
+            const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
+            R best = R(-1);
+            int bk = 0;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) {
+              const int k = qq * VE + e;
+              const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
+              const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
+              if (sc > best) {
+                best = sc;
+                bk = k;
+              }
+            }
+            prow[j] = best;
+            krow[j] = (uint16_t)bk;
+          } else {
+            prow[j] = R(-2);  // no update covers this position: its cache stays
+          }
+          qq += P.sq;
+          pl += P.spl;
+          if (qq >= G) {
+            qq -= G;
+            pl += 1;
+          }
+        }
+      }
+      __syncthreads();
+      const int npos = (rr1 - rr0) * ccw;
+      for (int t = tid; t < npos; t += NT) {
+        const R *pp = P.sh_ps + t * G;
+        if (pp[0] == R(-2)) continue;
+        const int rr = rr0 + t / ccw, pl = t % ccw;
+        const int pos = rr * W + cc0 + pl;
+        const uint16_t *pk = P.sh_pk + t * G;
+        R best = pp[0];
+        int bk = pk[0];
+        for (int g = 1; g < G; ++g)
+          if (pp[g] > best) {
+            best = pp[g];
+            bk = pk[g];
+          }
+        score_st(I.score + pos, best);
+        I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
+      }
+      __syncthreads();
+    }
+  }
+}
+
 // One workgroup is one worker of Alg. 3 (DiCoDiLe-Z).  Worker w of an instance
 // owns S_w, a block of a W1 x W2 balanced split of the valid domain, cut into
 // Mw balanced sub-domains of about tile1 x tile2 positions that it visits
@@ -410,6 +532,9 @@ template <class R, int NT> struct RoundSmem {
   unsigned long long tag[9];
   R delta[9];
   int nbr[9];
+  UCand<R> uc[9];
+  int nuc, ub[4];  // updates touching S_w and the bounding box of their patches
+  int ub_union;    // 1: apply them in one pass over the bounding box
 };
 
 // Runs worker w of instance I until its instance converges or stops.  Every
@@ -688,18 +813,60 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       tk_mark = t;
     }
 
-    // ---- phase B: apply accepted candidates that touch S_w (eq. beta_update)
-    for (int q = 0; q < nn; ++q) {
-      const unsigned long long tg = sh_tag[q];
-      const unsigned cpos = tag_pos(tg);
-      if (cpos == kNoPos) continue;
-      const int ch = (int)(cpos / (unsigned)W), cw0 = (int)(cpos - (unsigned)ch * (unsigned)W);
-      const int r1 = max(ch - I.L1 + 1, a1), r2 = min(ch + I.L1, b1);
-      const int c1 = max(cw0 - I.L2 + 1, a2), c2 = min(cw0 + I.L2, b2);
-      if (r1 >= r2 || c1 >= c2) continue;
+    // ---- phase B: apply the accepted candidates that touch S_w (eq. beta_update),
+    // all in one pass over the bounding box of their patches
+    if (tid == 0) {
+      int nu = 0, u1 = b1, u2 = a1, v1 = b2, v2 = a2;
+      for (int q = 0; q < nn; ++q) {
+        const unsigned long long tg = sh_tag[q];
+        const unsigned cpos = tag_pos(tg);
+        if (cpos == kNoPos) continue;
+        const int ch = (int)(cpos / (unsigned)W), cw0 = (int)(cpos - (unsigned)ch * (unsigned)W);
+        const int r1 = max(ch - I.L1 + 1, a1), r2 = min(ch + I.L1, b1);
+        const int c1 = max(cw0 - I.L2 + 1, a2), c2 = min(cw0 + I.L2, b2);
+        if (r1 >= r2 || c1 >= c2) continue;
+        UCand<R> &u = sm.uc[nu++];
+        u.k0 = tag_k0(tg);
+        u.ch = ch;
+        u.cw0 = cw0;
+        u.r1 = r1;
+        u.r2 = r2;
+        u.c1 = c1;
+        u.c2 = c2;
+        u.aoff = ((u.k0 * I.U1 - ch + I.L1 - 1) * I.U2 - cw0 + I.L2 - 1) * I.KS;
+        u.delta = sh_delta[q];
+        u1 = min(u1, r1);
+        u2 = max(u2, r2);
+        v1 = min(v1, c1);
+        v2 = max(v2, c2);
+        my_patch += (unsigned long long)(r2 - r1) * (c2 - c1);
+      }
+      sm.nuc = nu;
+      sm.ub[0] = u1;
+      sm.ub[1] = u2;
+      sm.ub[2] = v1;
+      sm.ub[3] = v2;
+      // One pass over the bounding box pays for small patches, whose cost is
+      // mostly per-update latency, when they fill at least half of it.  Large
+      // patches (over 1024 positions) are bandwidth-bound and go one by one:
+      // measured on 16x16 atoms (961-position patches) the pass saves 13% of
+      // the rounds' time, on 32x32 atoms (3969) it costs 7-20%.
+      long long area = 0;
+      for (int c = 0; c < nu; ++c)
+        area += (long long)(sm.uc[c].r2 - sm.uc[c].r1) * (sm.uc[c].c2 - sm.uc[c].c1);
+      sm.ub_union = nu > 1 && (long long)I.U1 * I.U2 <= 1024 && (long long)(u2 - u1) * (v2 - v1) <= area * 2;
+    }
+    __syncthreads();
+    if (sm.nuc > 0) {
       quiet = 0;
-      my_patch += (unsigned long long)(r2 - r1) * (c2 - c1);
-      patch_region<R, NT>(I, P, r1, r2, c1, c2, tag_k0(tg), ch, cw0, sh_delta[q]);
+      if (sm.ub_union || sm.nuc == 1) {
+        patch_union<R, NT>(I, P, sm.uc, sm.nuc, sm.ub[0], sm.ub[1], sm.ub[2], sm.ub[3]);
+      } else {
+        for (int c = 0; c < sm.nuc; ++c) {
+          const UCand<R> &u = sm.uc[c];
+          patch_region<R, NT>(I, P, u.r1, u.r2, u.c1, u.c2, u.k0, u.ch, u.cw0, u.delta);
+        }
+      }
     }
     // cache stores complete before the progress counter moves
     wait_vm();
