@@ -92,7 +92,7 @@ typedef struct {
   dcdl_dtype dtype;       /* precision of X, D, z_out and of the incremental beta/Z */
   int32_t no_soft_lock;   /* 1: disable the soft-lock test of eq. soft_lock (ablation of
                              Sec. 5 only; pair it with div_guard) */
-  int32_t threads;        /* threads per worker workgroup: 64 ... 1024 (powers of 2); 0 -> 256 */
+  int32_t threads;        /* threads per worker workgroup: 64, 128, 192, 256, 512 or 1024; 0 -> 256 */
   int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
   int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library */
   int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
@@ -280,7 +280,7 @@ typedef struct {
   int32_t no_graph;     /* 1: enqueue the per-instance set-up and check kernels directly
                            instead of recording them as HIP graphs */
   int32_t workers;      /* workgroups spread over the instances; 0 -> every co-resident slot */
-  int32_t threads;      /* threads per worker workgroup (64 ... 1024); 0 -> 256 */
+  int32_t threads;      /* threads per worker workgroup (64, 128, 192, 256, 512, 1024); 0 -> 256 */
   int32_t tile[2];      /* sub-domain size; 0 -> 2 L_i (Sec. 3) */
   int32_t max_polish;   /* extra passes for instances failing the final check; 0 -> 2 */
   int32_t inner;        /* sub-domain visits per worker per round; 0 -> 1 */
@@ -375,7 +375,7 @@ typedef struct {
   int32_t max_workers;      /* workgroups of one request at most; 0 -> 128 */
   int32_t slice_rounds;     /* rounds per launch between admissions; 0 -> 64 */
   int32_t max_active;       /* admitted requests at most; 0 -> 256 */
-  int32_t threads;          /* threads per worker workgroup (64, 128, 256); 0 -> 256 */
+  int32_t threads;          /* threads per worker workgroup (64, 128, 192, 256); 0 -> 256 */
   int32_t tile[2];          /* sub-domain size; 0 -> 2 L_i (d = 1: tile[0] is the length) */
   int32_t max_polish;       /* extra passes for requests failing the final check; 0 -> 2 */
   int32_t reserved;

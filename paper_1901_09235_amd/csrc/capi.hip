@@ -367,6 +367,21 @@ int capacity(DeviceState *ds, int *cap) {
   return DCDL_OK;
 }
 
+// Workgroup sizes the round kernel is built for.
+bool valid_nt(int nt) { return nt == 64 || nt == 128 || nt == 192 || nt == 256 || nt == 512 || nt == 1024; }
+
+template <class R>
+int capacity_nt(DeviceState *ds, int nt, int *cap) {
+  switch (nt) {
+    case 64: return capacity<R, 64>(ds, cap);
+    case 128: return capacity<R, 128>(ds, cap);
+    case 192: return capacity<R, 192>(ds, cap);
+    case 512: return capacity<R, 512>(ds, cap);
+    case 1024: return capacity<R, 1024>(ds, cap);
+    default: return capacity<R, 256>(ds, cap);
+  }
+}
+
 int plan_grid(const Geom &g, int ndim, const dcdl_csc_opts *o, int cap, Plan *p) {
   p->tile1 = o->tile[0] > 0 ? o->tile[0] : (ndim == 1 ? 1 : 2 * g.L1);
   p->tile2 = o->tile[1] > 0 ? o->tile[1] : 2 * g.L2;
@@ -417,6 +432,7 @@ int launch_rounds(hipStream_t stream, int nt, Inst<R> *d_inst, int *d_wg, int nw
   const void *fn;
   switch (nt) {
     case 64: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 64>); break;
+    case 192: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 192>); break;
     case 128: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 128>); break;
     case 512: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 512>); break;
     case 1024: fn = reinterpret_cast<const void *>(lgcd_rounds<R, 1024>); break;
@@ -439,13 +455,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   g.KS = atom_stride(g.K, (int)sizeof(R));
   const long long HW = (long long)g.H * g.W, nz = HW * g.KS;
   const long long nA = (long long)g.K * g.U1 * g.U2 * g.KS;
-  const int nt = (o->threads == 64 || o->threads == 128 || o->threads == 512 || o->threads == 1024) ? o->threads : 256;
-  int cap = 0, rc;
-  if (nt == 64) rc = capacity<R, 64>(ds, &cap);
-  else if (nt == 128) rc = capacity<R, 128>(ds, &cap);
-  else if (nt == 512) rc = capacity<R, 512>(ds, &cap);
-  else if (nt == 1024) rc = capacity<R, 1024>(ds, &cap);
-  else rc = capacity<R, 256>(ds, &cap);
+  const int nt = valid_nt(o->threads) ? o->threads : 256;
+  int cap = 0, rc = capacity_nt<R>(ds, nt, &cap);
   if (rc) return rc;
   Plan pl;
   if ((rc = plan_grid(g, ndim, o, cap, &pl))) return rc;
@@ -792,9 +803,8 @@ int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dc
   if (!(opts->lambda > 0)) return fail(DCDL_EINVAL, "lambda must be > 0");
   if (!(opts->tol >= 0)) return fail(DCDL_EINVAL, "tol must be >= 0");
   if (opts->dtype != DCDL_F32 && opts->dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype");
-  if (opts->threads != 0 && opts->threads != 64 && opts->threads != 128 && opts->threads != 256 &&
-      opts->threads != 512 && opts->threads != 1024)
-    return fail(DCDL_EINVAL, "threads must be 64, 128, 256, 512 or 1024");
+  if (opts->threads != 0 && !valid_nt(opts->threads))
+    return fail(DCDL_EINVAL, "threads must be 64, 128, 192, 256, 512 or 1024");
   if (opts->tile[0] < 0 || opts->tile[1] < 0 || opts->grid[0] < 0 || opts->grid[1] < 0)
     return fail(DCDL_EINVAL, "negative tile or grid");
   if (opts->max_rounds > (1ll << 30)) return fail(DCDL_EINVAL, "max_rounds above 2^30");

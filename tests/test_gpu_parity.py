@@ -115,7 +115,7 @@ def test_csc_signal_1d_fp64_every_grid(lib, W):
     assert info["n_updates"] > 0
 
 
-@pytest.mark.parametrize("threads", [64, 256])
+@pytest.mark.parametrize("threads", [64, 192, 256])
 def test_csc_small_image_fp32(lib, threads):
     pb = _small_image(7)
     _solve_and_compare(lib, pb, torch.float32, threads=threads)
