@@ -88,6 +88,11 @@ def _load():
                                          _i64]
     lib.orc_dicodile_z.restype = ctypes.c_int
     lib.orc_dict_stats.argtypes = shp + [_dp, _dp, _dp, _dp]
+    lib.orc_draw.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64]
+    lib.orc_draw.restype = ctypes.c_uint64
+    lib.orc_rcd.argtypes = shp + [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                  ctypes.c_uint64, _i64, ctypes.c_int, _dp, ctypes.POINTER(LgcdInfo)]
+    lib.orc_rcd.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -220,8 +225,8 @@ def lgcd(X, D, lam: float, tol: float, positive: bool = False, tile=None,
     P, T1, T2, K, L1, L2 = s
     if tile is None:
         tile = _default_tile(L1, L2, is_1d)
-    elif is_1d and np.isscalar(tile):
-        tile = (1, int(tile))
+    elif np.isscalar(tile):
+        tile = (1, int(tile)) if is_1d else (int(tile), int(tile))
     Z = np.zeros(_zshape(*s)) if z0 is None else _in_z(z0, _zshape(*s), is_1d).copy()
     info = LgcdInfo()
     rc = _load().orc_lgcd(*s, _p(X3), _p(D4), float(lam), float(tol), int(positive),
@@ -230,6 +235,32 @@ def lgcd(X, D, lam: float, tol: float, positive: bool = False, tile=None,
                           ctypes.byref(info))
     if rc != 0:
         raise ValueError("orc_lgcd rejected its arguments")
+    d = {f: getattr(info, f) for f, _ in LgcdInfo._fields_ if f != "pad"}
+    return _out_z(Z, is_1d), d
+
+
+def draw(seed: int, stream: int, n: int) -> int:
+    """The n-th value of stream `stream` of the randomized rule's generator
+    (SplitMix64 of `seed`, counter n + stream * 2^40)."""
+    return int(_load().orc_draw(int(seed) & (2 ** 64 - 1), int(stream), int(n)))
+
+
+def rcd(X, D, lam: float, tol: float, seed: int = 0, positive: bool = False, certify: bool = True,
+        max_epochs: int = 10 ** 6):
+    """Sequential randomized coordinate descent (Sec. 3's random selection
+    rule; the RCD of Sec. 5's comparison).  Coordinates are drawn uniformly
+    with `draw(seed, 0, n)`; the run stops after an epoch (H W draws) whose
+    final scan finds no move scoring >= tol.  Returns (Z, info dict) with
+    n_sweeps = epochs."""
+    X3, D4, is_1d = _as2d(X, D)
+    s = _shape(X3, D4)
+    Z = np.zeros(_zshape(*s))
+    info = LgcdInfo()
+    rc = _load().orc_rcd(*s, _p(X3), _p(D4), float(lam), float(tol), int(positive),
+                         int(seed) & (2 ** 64 - 1), int(max_epochs), int(certify), _p(Z),
+                         ctypes.byref(info))
+    if rc != 0:
+        raise ValueError("orc_rcd rejected its arguments")
     d = {f: getattr(info, f) for f, _ in LgcdInfo._fields_ if f != "pad"}
     return _out_z(Z, is_1d), d
 

@@ -361,6 +361,93 @@ int orc_lgcd(int P, int64_t T1, int64_t T2, int K, int L1, int L2,
   return 0;
 }
 
+/* Counter-based generator of the randomized selection rule: SplitMix64
+ * (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+ * OOPSLA 2014).  Its n-th output from the seed s is the mixing function
+ *   z <- (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9
+ *   z <- (z ^ (z >> 27)) * 0x94d049bb133111eb
+ *   z <- z ^ (z >> 31)
+ * applied to z = s + (n + 1) * 0x9e3779b97f4a7c15 (mod 2^64).  Stream j (one
+ * per worker) uses the counter n + j * 2^40, so stream 0 is the plain
+ * SplitMix64 sequence of s. */
+uint64_t orc_draw(uint64_t seed, uint64_t stream, uint64_t n) {
+  uint64_t z = seed + ((stream << 40) + n + 1) * 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+/* Randomized coordinate descent: the random selection rule Sec. 3 names
+ * beside the cyclic and greedy ones, the "RCD" of the comparison in Sec. 5.
+ *
+ * Draw n = 0, 1, ... takes j = orc_draw(seed, 0, n) mod (K H W), the position
+ * p = j / K of Omega_Z in raster order and the atom k = j mod K, and moves
+ * Z_k[p] to its closed-form target (eq. pb_coord) when the move scores at
+ * least tol and Delta Z != 0 (score as in orc_lgcd).  An epoch is H W draws;
+ * after each one every coordinate is scored, and the run stops when none
+ * scores >= tol with a non-zero move (the certificate of orc_lgcd's sweep
+ * rule), or after max_epochs epochs.  info->n_sweeps counts epochs.
+ * Returns 0 on success, -1 on bad arguments or allocation failure. */
+int orc_rcd(int P, int64_t T1, int64_t T2, int K, int L1, int L2,
+            const double *X, const double *D, double lambda, double tol,
+            int positive, uint64_t seed, int64_t max_epochs, int certify,
+            double *Z, orc_lgcd_info *info) {
+  if (P < 1 || K < 1 || L1 < 1 || L2 < 1 || T1 < L1 || T2 < L2 || !(lambda > 0.0) || tol < 0.0)
+    return -1;
+  const int64_t H = T1 - L1 + 1, W = T2 - L2 + 1, HW = H * W, nz = (int64_t)K * HW;
+  const int U1 = 2 * L1 - 1, U2 = 2 * L2 - 1;
+  double *n = (double *)malloc(sizeof(double) * (size_t)K);
+  double *C = (double *)malloc(sizeof(double) * (size_t)K * K * U1 * U2);
+  double *beta = (double *)malloc(sizeof(double) * (size_t)nz);
+  if (!n || !C || !beta) {
+    free(n); free(C); free(beta);
+    return -1;
+  }
+  orc_atom_norms(K, P, L1, L2, D, n);
+  orc_dtd(K, P, L1, L2, D, C);
+  memset(Z, 0, sizeof(double) * (size_t)nz);
+  orc_beta(P, T1, T2, K, L1, L2, X, D, Z, beta);
+  memset(info, 0, sizeof(*info));
+  info->t_kkt_s = -1.0;
+  info->sweeps_kkt = -1;
+  const double t0 = now_s();
+  uint64_t draw = 0;
+  int converged = 0;
+  int64_t epoch = 0;
+  while (epoch < max_epochs) {
+    for (int64_t q = 0; q < HW; ++q, ++draw) {
+      const uint64_t j = orc_draw(seed, 0, draw) % (uint64_t)nz;
+      const int64_t p = (int64_t)(j / (uint64_t)K);
+      const int k = (int)(j % (uint64_t)K);
+      const int64_t a1 = p / W, a2 = p % W;
+      const int64_t i = IDX3(k, a1, a2, H, W);
+      const double z = Z[i], zn = coord_target(beta[i], n[k], lambda, positive);
+      if (move_score(z, zn, tol, certify) < tol || zn == z) continue;
+      info->cost_decrease += delta_cost(n[k], beta[i], z, zn, lambda);
+      beta_patch(K, L1, L2, H, W, C, k, a1, a2, zn - z, beta);
+      Z[i] = zn;
+      ++info->n_updates;
+    }
+    ++epoch;
+    int moves = 0;
+    for (int k = 0; k < K && !moves; ++k)
+      for (int64_t p = 0; p < HW && !moves; ++p) {
+        const int64_t i = IDX3(k, p / W, p % W, H, W);
+        const double zn = coord_target(beta[i], n[k], lambda, positive);
+        moves = move_score(Z[i], zn, tol, certify) >= tol && zn != Z[i];
+      }
+    if (!moves) {
+      converged = 1;
+      break;
+    }
+  }
+  info->n_sweeps = epoch;
+  info->converged = converged;
+  info->t_solve_s = now_s() - t0;
+  free(n); free(C); free(beta);
+  return 0;
+}
+
 typedef struct {
   int64_t n_rounds;        /* bulk-synchronous rounds executed */
   int64_t n_sweeps;        /* sweeps (M_max rounds each) */

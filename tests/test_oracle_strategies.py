@@ -1,0 +1,179 @@
+"""Pins of the oracle's coordinate-selection rules (Sec. 3: cyclic, random and
+greedy selection, of which locally greedy selection is the family between the
+two extremes; Sec. 5 compares greedy, randomized and locally greedy CD).
+
+Greedy CD is LGCD with one sub-domain (tile = the whole domain) and cyclic CD
+is LGCD with one-position sub-domains (tile = 1); randomized CD is its own
+routine (``oracle.rcd``) driven by a counter-based SplitMix64 generator.  Each
+rule is pinned against an exact enumeration, a library Lasso, the published
+known-answer sequence of the generator, or a first step computed with scipy.
+"""
+import numpy as np
+import pytest
+from scipy import signal, stats
+
+import oracle
+from oracle import brute
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _dict(rng, K, P, L):
+    shape = (K, P) + (tuple(L) if isinstance(L, tuple) else (L,))
+    D = rng.standard_normal(shape)
+    return D / np.sqrt((D.reshape(K, -1) ** 2).sum(axis=1)).reshape((K,) + (1,) * (D.ndim - 1))
+
+
+def _image_problem(seed, size=20, K=3, L=(4, 4), P=2):
+    rng = _rng(seed)
+    D = _dict(rng, K, P, L)
+    H, W = size - L[0] + 1, size - L[1] + 1
+    Zt = (rng.random((K, H, W)) < 0.03) * rng.uniform(0.5, 1.5, (K, H, W))
+    X = np.stack([sum(signal.convolve(Zt[k], D[k, p]) for k in range(K)) for p in range(P)])
+    return X + 0.1 * rng.standard_normal(X.shape), D
+
+
+def _signal_problem(seed, T=240, K=3, L=12, P=2):
+    rng = _rng(seed)
+    D = _dict(rng, K, P, L)
+    Zt = (rng.random((K, T - L + 1)) < 0.02) * rng.standard_normal((K, T - L + 1))
+    X = np.stack([sum(np.convolve(Zt[k], D[k, p]) for k in range(K)) for p in range(P)])
+    return X + 0.1 * rng.standard_normal(X.shape), D
+
+
+# ------------------------------------------------------------------ generator
+
+def test_draw_is_splitmix64_known_answers():
+    """Stream 0 is SplitMix64 of the seed: its widely reproduced known-answer
+    outputs for seed 1234567, and the first output for seed 0."""
+    assert [oracle.draw(1234567, 0, n) for n in range(5)] == [
+        6457827717110365317, 3203168211198807973, 9817491932198370423,
+        4593380528125082431, 16408922859458223821]
+    assert oracle.draw(0, 0, 0) == 0xE220A8397B1DCDAF
+
+
+def test_draw_streams_and_uniformity():
+    """Stream j is the same sequence shifted by j 2^40 draws, and coordinates
+    drawn as value mod N are uniform (chi-square)."""
+    for j, n in ((1, 0), (3, 17), (1000, 5)):
+        assert oracle.draw(99, j, n) == oracle.draw(99, 0, n + j * 2 ** 40)
+    N = 97
+    counts = np.bincount([oracle.draw(7, 2, n) % N for n in range(40_000)], minlength=N)
+    assert stats.chisquare(counts).pvalue > 1e-4
+
+
+# ------------------------------------------------------------ exact minimisers
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_every_rule_matches_brute_force(positive):
+    """Greedy, cyclic and randomized CD reach the enumerated Lasso optimum."""
+    for seed in range(60, 66):
+        rng = _rng(seed)
+        D = _dict(rng, 2, 1, 3)
+        X = rng.standard_normal((1, 7))
+        A = brute.design_matrix(D, 7)
+        lam = 0.2 * float(np.abs(A.T @ X.ravel()).max())
+        _, fstar = brute.brute_force_lasso(A, X.ravel(), lam, positive=positive)
+        runs = {
+            "gcd": oracle.lgcd(X, D, lam, 1e-14, positive=positive, tile=10 ** 6)[0],
+            "cyclic": oracle.lgcd(X, D, lam, 1e-14, positive=positive, tile=1)[0],
+            "rcd": oracle.rcd(X, D, lam, 1e-14, seed=seed, positive=positive)[0],
+        }
+        for name, Z in runs.items():
+            assert oracle.objective(X, D, Z, lam) == pytest.approx(fstar, rel=1e-12), name
+
+
+def test_rcd_matches_sklearn_lasso():
+    from sklearn.linear_model import Lasso
+    rng = _rng(70)
+    D, T = _dict(rng, 2, 1, (3, 3)), (11, 12)
+    X = rng.standard_normal((1,) + T)
+    A = brute.design_matrix(D, T)
+    y = X.ravel()
+    lam = 0.1 * oracle.lambda_max(X, D)
+    model = Lasso(alpha=lam / y.size, fit_intercept=False, tol=1e-14, max_iter=200000)
+    model.fit(A, y)
+    f_sk = brute.lasso_objective(A, y, model.coef_, lam)
+    Z, info = oracle.rcd(X, D, lam, 1e-12 * lam, seed=3)
+    assert info["converged"] == 1
+    assert oracle.objective(X, D, Z, lam) == pytest.approx(f_sk, rel=1e-9)
+
+
+@pytest.mark.parametrize("oned", [True, False])
+def test_rules_agree_and_certify(oned):
+    """On a larger problem every rule stops on the same minimiser (the Lasso is
+    strictly convex here) with the certificate of the sweep rule: strict KKT
+    <= max_k n_k tol / lambda."""
+    X, D = _signal_problem(71) if oned else _image_problem(72)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    tol = 1e-9 * lam
+    nmax = max(float((D[k] ** 2).sum()) for k in range(D.shape[0]))
+    ref = None
+    for name, (Z, info) in {
+        "lgcd": oracle.lgcd(X, D, lam, tol),
+        "gcd": oracle.lgcd(X, D, lam, tol, tile=10 ** 6),
+        "cyclic": oracle.lgcd(X, D, lam, tol, tile=1),
+        "rcd": oracle.rcd(X, D, lam, tol, seed=11),
+    }.items():
+        assert info["converged"] == 1, name
+        f = oracle.objective(X, D, Z, lam)
+        ref = f if ref is None else ref
+        assert f == pytest.approx(ref, rel=1e-10), name
+        assert oracle.kkt(X, D, Z, lam) <= nmax * tol / lam * (1 + 1e-9), name
+
+
+def test_rcd_reproducible_per_seed():
+    X, D = _signal_problem(73)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    Z1, i1 = oracle.rcd(X, D, lam, 1e-10 * lam, seed=5)
+    Z2, i2 = oracle.rcd(X, D, lam, 1e-10 * lam, seed=5)
+    Z3, i3 = oracle.rcd(X, D, lam, 1e-10 * lam, seed=6)
+    assert np.array_equal(Z1, Z2) and i1["n_updates"] == i2["n_updates"]
+    assert i3["n_updates"] != i1["n_updates"]
+    assert oracle.objective(X, D, Z3, lam) == pytest.approx(oracle.objective(X, D, Z1, lam), rel=1e-10)
+
+
+def test_rcd_sum_of_cost_decreases_is_objective_change():
+    """Prop. A.1's per-update decrease summed over the random updates."""
+    X, D = _image_problem(74)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    Z, info = oracle.rcd(X, D, lam, 1e-10 * lam, seed=2)
+    f0 = oracle.objective(X, D, np.zeros_like(Z), lam)
+    assert f0 - oracle.objective(X, D, Z, lam) == pytest.approx(info["cost_decrease"], rel=1e-10)
+
+
+# ------------------------------------------------------------------ first steps
+
+def _best_move_from_zero(X, D, lam):
+    """Closed-form targets of every coordinate at Z = 0 (eq. pb_coord), from
+    scipy's valid correlation."""
+    K, P = D.shape[:2]
+    G = np.stack([sum(signal.correlate(X[p], D[k, p], mode="valid") for p in range(P)) for k in range(K)])
+    n = (D.reshape(K, -1) ** 2).sum(axis=1)
+    return np.sign(G) * np.maximum(np.abs(G) - lam, 0) / n.reshape((K,) + (1,) * (G.ndim - 1))
+
+
+def test_greedy_first_update_is_the_global_best():
+    X, D = _image_problem(75)
+    lam = 0.1 * oracle.lambda_max(X, D)
+    T0 = _best_move_from_zero(X, D, lam)
+    Z, info = oracle.lgcd(X, D, lam, 0.0, tile=10 ** 6, max_sweeps=1)
+    assert info["n_updates"] == 1
+    nz = np.flatnonzero(Z)
+    assert nz.size == 1 and nz[0] == np.argmax(np.abs(T0))
+    assert Z.ravel()[nz[0]] == pytest.approx(T0.ravel()[nz[0]], rel=1e-12)
+
+
+def test_cyclic_first_position_takes_its_best_atom():
+    """Tile 1: the first visit is position (0, 0), whose best atom moves to
+    its target from zero; nothing else has moved before it."""
+    X, D = _image_problem(76)
+    lam = 0.02 * oracle.lambda_max(X, D)
+    T0 = _best_move_from_zero(X, D, lam)
+    assert np.abs(T0[:, 0, 0]).max() > 0
+    Z, _ = oracle.lgcd(X, D, lam, 0.0, tile=1, max_sweeps=1)
+    k = int(np.argmax(np.abs(T0[:, 0, 0])))
+    assert Z[k, 0, 0] == pytest.approx(T0[k, 0, 0], rel=1e-12)
+    assert np.count_nonzero(Z[:, 0, 0]) == 1
