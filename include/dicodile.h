@@ -69,6 +69,24 @@ typedef enum {
   DCDL_CORR_DIRECT = 4   /* vector FMA in the data's precision, no matrix cores */
 } dcdl_corr_prec;
 
+/* Coordinate-selection rule of the solve (dcdl_csc_opts.strategy).  Sec. 3
+ * names the cyclic, random and greedy rules and builds the locally greedy one
+ * between them; Sec. 5 compares greedy, randomized and locally greedy CD.
+ * Every rule runs inside the same worker grid, soft-lock and stopping
+ * certificate (no move scoring >= tol anywhere). */
+typedef enum {
+  DCDL_SELECT_LGCD = 0,    /* greedy within sub-domains of opts->tile (Alg. 1) */
+  DCDL_SELECT_GREEDY = 1,  /* one sub-domain per worker: the worker's whole domain (GCD) */
+  DCDL_SELECT_CYCLIC = 2,  /* one-position sub-domains visited in raster order: cyclic CD over
+                              positions, greedy over the K atoms of a position */
+  DCDL_SELECT_RANDOM = 3   /* one coordinate (position and atom) per round, drawn uniformly from the
+                              worker's domain with the counter-based SplitMix64 generator: worker w's
+                              n-th draw is SplitMix64 of opts->seed at counter n + w 2^40, and
+                              j = draw mod (K |S_w|) picks position j / K (raster order in S_w) and
+                              atom j mod K.  A worker checks its whole domain once per |S_w| draws
+                              for the stopping certificate */
+} dcdl_select;
+
 /* Problem shape.  ndim = 1: T[0] = T, L[0] = L (T[1], L[1] ignored).
  * ndim = 2: T = (T1, T2), L = (L1, L2).  Requires 1 <= L_i <= T_i, P >= 1,
  * 1 <= K <= 1024. */
@@ -108,6 +126,11 @@ typedef struct {
   double div_guard;       /* stop with DCDL_EDIVERGED if |Z| exceeds this (0 -> off) */
   double timeout_s;       /* wall-clock cap for the whole call (0 -> none) */
   double kkt_target;      /* final strict-KKT acceptance, in units of lambda; 0 -> 1e-4 */
+  int32_t strategy;       /* dcdl_select; 0 -> LGCD.  GREEDY and CYCLIC override tile, RANDOM
+                             ignores tile and inner.  Only dicodile_csc (and dicodile_cdl's CSC
+                             steps) accept a rule other than LGCD */
+  int32_t reserved;
+  uint64_t seed;          /* seed of the RANDOM rule's generator */
 } dcdl_csc_opts;
 
 /* Filled by dicodile_csc when `info` is not NULL (host memory). */

@@ -29,6 +29,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM",
           -4: "EDIVERGED", -5: "ETIMEOUT", -6: "ENODEV"}
 F32, F64 = 0, 1
 CORR_PREC = {"auto": 0, "f64": 1, "bf16": 2, "bf16x3": 3, "direct": 4}
+SELECT = {"lgcd": 0, "greedy": 1, "cyclic": 2, "random": 3}
 
 
 class DicodileError(RuntimeError):
@@ -51,7 +52,8 @@ class CscOpts(ctypes.Structure):
                 ("refresh_every", ctypes.c_int32), ("max_polish", ctypes.c_int32),
                 ("inner", ctypes.c_int32), ("beta_prec", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
-                ("kkt_target", ctypes.c_double)]
+                ("kkt_target", ctypes.c_double), ("strategy", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class CscInfo(ctypes.Structure):
@@ -257,7 +259,7 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
               div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0,
-              beta_prec=0) -> CscOpts:
+              beta_prec=0, strategy=0, seed=0) -> CscOpts:
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -273,6 +275,11 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
     o.kkt_target = float(kkt_target)
     o.inner = int(inner)
     o.beta_prec = CORR_PREC[beta_prec] if isinstance(beta_prec, str) else int(beta_prec)
+    if isinstance(strategy, str):
+        if strategy not in SELECT:
+            raise DicodileError(-1, f"unknown selection rule {strategy!r} (one of {sorted(SELECT)})")
+        strategy = SELECT[strategy]
+    o.strategy, o.seed = int(strategy), int(seed) & (2 ** 64 - 1)
     return o
 
 
@@ -289,8 +296,10 @@ def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
 
     Keyword options mirror dcdl_csc_opts: positive, certify, grid, tile,
     threads, warm_start, refresh_every, max_polish, max_rounds, div_guard,
-    timeout_s, kkt_target, no_soft_lock.  A NOT_CONVERGED status is reported
-    in info['status']; errors raise DicodileError."""
+    timeout_s, kkt_target, no_soft_lock, inner, beta_prec, strategy ("lgcd",
+    "greedy", "cyclic", "random" or the dcdl_select code) and seed.  A
+    NOT_CONVERGED status is reported in info['status']; errors raise
+    DicodileError."""
     torch = _torch()
     lib = load()
     _device_tensor(X, "X")

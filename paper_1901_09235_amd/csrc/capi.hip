@@ -422,7 +422,16 @@ int plan_grid(const Geom &g, int ndim, const dcdl_csc_opts *o, int cap, Plan *p)
   const int ext1 = (g.H + W1 - 1) / W1, ext2 = (g.W + W2 - 1) / W2;
   p->W1 = W1;
   p->W2 = W2;
+  // the rules other than LGCD keep the grid chosen above and fix the sub-domains
+  if (o->strategy == DCDL_SELECT_GREEDY) {
+    p->tile1 = g.H;
+    p->tile2 = g.W;
+  } else if (o->strategy == DCDL_SELECT_CYCLIC) {
+    p->tile1 = 1;
+    p->tile2 = 1;
+  }
   p->mmax = std::max(1, (ext1 + p->tile1 / 2) / p->tile1) * std::max(1, (ext2 + p->tile2 / 2) / p->tile2);
+  if (o->strategy == DCDL_SELECT_RANDOM) p->mmax = ext1 * ext2;  // draws per epoch
   return DCDL_OK;
 }
 
@@ -528,6 +537,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   hi.positive = o->positive;
   hi.certify = o->certify;
   hi.soft_lock = o->no_soft_lock ? 0 : 1;
+  hi.strategy = o->strategy;
+  hi.seed = o->seed;
   hi.lambda = lam;
   hi.tol = tol;
   hi.div_guard = (R)o->div_guard;
@@ -808,6 +819,8 @@ int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dc
   if (opts->tile[0] < 0 || opts->tile[1] < 0 || opts->grid[0] < 0 || opts->grid[1] < 0)
     return fail(DCDL_EINVAL, "negative tile or grid");
   if (opts->max_rounds > (1ll << 30)) return fail(DCDL_EINVAL, "max_rounds above 2^30");
+  if (opts->strategy < DCDL_SELECT_LGCD || opts->strategy > DCDL_SELECT_RANDOM)
+    return fail(DCDL_EINVAL, "unknown selection rule %d", opts->strategy);
   PROLOGUE();
   if (opts->dtype == DCDL_F32)
     return csc_impl<float>(ds, stream, g, shape->ndim, (const float *)X, (const float *)D, opts, (float *)z_out, info);

@@ -81,10 +81,12 @@ template <class R> struct Inst {
   int H, W;
   int W1, W2, tile1, tile2, mmax, wg_base;
   int inner;  // sub-domain visits per round (at most Mw); 0 -> 1
-  int positive, certify, soft_lock, pad0;
+  int positive, certify, soft_lock;
+  int strategy;  // dcdl_select: 0 LGCD, 1 greedy, 2 cyclic (both through tile1/tile2), 3 random
   R lambda, tol, div_guard;
   long long max_rounds;
   long long budget_ticks;  // wall-clock cap of one launch, 100 MHz clock ticks
+  unsigned long long seed;  // generator seed of the random rule
   R *beta, *z;
   R *score;        // shared: coherent accesses only
   uint32_t *meta;  // private to the owning worker
@@ -121,6 +123,18 @@ __device__ __forceinline__ R move_score(R z, R zn, R tol, int certify) {
   if (certify && z != R(0) && (zn == R(0) || ((zn > R(0)) != (z > R(0)))))
     dz = dz > tol ? dz : tol;
   return dz;
+}
+
+// Counter-based draw of the random selection rule: SplitMix64 (Steele, Lea
+// and Flood, OOPSLA 2014).  Its n-th output from seed s mixes
+// s + (n + 1) * 0x9e3779b97f4a7c15 with two xor-shift-multiply steps and a
+// final xor-shift; worker w draws at counter n + w * 2^40.
+__device__ __forceinline__ unsigned long long sm64_draw(unsigned long long seed, unsigned long long w,
+                                                        unsigned long long n) {
+  unsigned long long x = seed + ((w << 40) + n + 1ull) * 0x9e3779b97f4a7c15ull;
+  x = (x ^ (x >> 30)) * 0xbf58476d1ce4e5b9ull;
+  x = (x ^ (x >> 27)) * 0x94d049bb133111ebull;
+  return x ^ (x >> 31);
 }
 
 __device__ __forceinline__ int part_start(int j, int N, int Wn) {
@@ -517,9 +531,16 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
 // sizes of at least L_i keep every interaction between grid neighbours.
 //
 // Stopping: a worker is quiet once its last Mw visits found no move scoring
-// >= tol and no patch touched S_w since.  When every worker reports quiet at
-// the end of the same round, every coordinate's move is below tol and no
-// further update can happen: all workers exit.
+// >= tol and no patch touched S_w since (random rule: once the scan at the
+// end of its last epoch found none and no patch touched S_w since).  When
+// every worker reports quiet at the end of the same round, every
+// coordinate's move is below tol and no further update can happen: all
+// workers exit.
+//
+// Under the random rule a candidate's score is that of its drawn coordinate,
+// at most the cached best of its position, so of two interacting candidates
+// the soft-lock test still rejects at least one: each sees the other's
+// position holding a score >= its own (ties go to the lower worker index).
 template <class R, int NT> struct RoundSmem {
   static constexpr int LBUF = 4096;
   R ps[LBUF];
@@ -563,7 +584,12 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   const int ext1 = b1 - a1, ext2 = b2 - a2;
   const int nb1 = max(1, (ext1 + I.tile1 / 2) / I.tile1), nb2 = max(1, (ext2 + I.tile2 / 2) / I.tile2);
   const int Mw = nb1 * nb2;
-  const int inner = I.inner > 0 ? min(I.inner, Mw) : 1;
+  // random rule: one drawn coordinate per round; a scan of S_w every npw
+  // draws (an epoch) decides whether the worker is quiet
+  const bool rnd = I.strategy == 3;
+  const int npw = ext1 * ext2;
+  const int inner = rnd ? 1 : (I.inner > 0 ? min(I.inner, Mw) : 1);
+  const int qthr = rnd ? 1 : Mw;  // quiet count of a worker with no pending move
   // candidates at w0 in [in_lo, in_hi[ patch nothing of the band neighbours read
   const int in_lo1 = wi > 0 ? a1 + 2 * (I.L1 - 1) : a1, in_hi1 = wi < I.W1 - 1 ? b1 - 2 * (I.L1 - 1) : b1;
   const int in_lo2 = wj > 0 ? a2 + 2 * (I.L2 - 1) : a2, in_hi2 = wj < I.W2 - 1 ? b2 - 2 * (I.L2 - 1) : b2;
@@ -641,7 +667,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     // interior candidates are applied only if neither lies in the other's
     // V (they cannot interact); other candidates wait for the next cycle.
     R bs = R(-1);
-    int bp = 0x7fffffff;
+    int bp = 0x7fffffff, bk = 0;
     bool has = false;
     int hh0 = 0, hw0 = 0;
     long long restart = -1;  // first visit whose candidate had to wait: next round starts there
@@ -650,6 +676,32 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       const int m = (int)(cursor % Mw);
       ++cursor;
       ++my_visit;
+      if (rnd) {
+        const unsigned long long u = sm64_draw(I.seed, (unsigned long long)w, (unsigned long long)visit);
+        const unsigned long long j = u % ((unsigned long long)npw * (unsigned long long)K);
+        const unsigned long long jp = j / (unsigned long long)K;
+        const int k = (int)(j - jp * (unsigned long long)K);
+        const int hh = a1 + (int)jp / ext2, ww = a2 + (int)jp % ext2;
+        const int pos = hh * W + ww;
+        if (tid == 0) {
+          const long long i0 = (long long)pos * I.KS + k;
+          sh_rs[0] = move_score(I.z[i0], st_target(I.beta[i0], I.lambda, sh_inv_n[k], I.positive), I.tol,
+                                I.certify);
+        }
+        __syncthreads();
+        const R sc = sh_rs[0];
+        __syncthreads();
+        if (!(sc >= I.tol && sc > R(0))) continue;
+        quiet = 0;
+        ++my_cand;
+        has = true;
+        bs = sc;
+        bp = pos;
+        bk = k;
+        hh0 = hh;
+        hw0 = ww;
+        continue;
+      }
       const int bi = m / nb2, bj = m - (m / nb2) * nb2;
       const int s1 = a1 + part_start(bi, ext1, nb1), e1 = a1 + part_start(bi + 1, ext1, nb1);
       const int s2 = a2 + part_start(bj, ext2, nb2), e2 = a2 + part_start(bj + 1, ext2, nb2);
@@ -753,7 +805,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
         if (locked) {
           ++my_lock;
         } else {
-          const int k0 = meta_argk(I.meta[bp]);
+          const int k0 = rnd ? bk : meta_argk(I.meta[bp]);
           const long long i0 = (long long)bp * I.KS + k0;
           const R zc = I.z[i0];
           const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
@@ -871,13 +923,25 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     // cache stores complete before the progress counter moves
     wait_vm();
     __syncthreads();
+    if (rnd && cursor % npw == 0) {
+      // end of an epoch: the worker is quiet if no position of S_w holds a
+      // move scoring >= tol (every later patch of S_w clears it again)
+      R mx = R(-1);
+      int mp = 0;
+      for (int t = tid; t < npw; t += NT) {
+        const R sc = score_ld(I.score + (a1 + t / ext2) * W + a2 + t % ext2);
+        if (sc > mx) mx = sc;
+      }
+      block_argmax<R, NT>(mx, mp, sh_rs, sh_ri);
+      quiet = (mx >= I.tol && mx > R(0)) ? 0 : 1;
+    }
     if (tid == 0) {
       st_shared_i32(I.prog + w, r + 1);
       tk_app += __builtin_amdgcn_s_memrealtime() - tk_mark;
       // ---- stopping consensus: quiet counts of round r
       const int slot = r % kRing;
       int *done = I.ring, *qcount = I.ring + kRing;
-      if (quiet >= Mw) __hip_atomic_fetch_add(&qcount[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (quiet >= qthr) __hip_atomic_fetch_add(&qcount[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       wait_vm();
       const int old = __hip_atomic_fetch_add(&done[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (old == nW - 1) {
@@ -907,7 +971,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     atomicAdd(&I.ctl->tk_collect, tk_col);
     atomicAdd(&I.ctl->tk_apply, tk_app);
     atomicMax(&I.ctl->max_round, r);
-    atomicMax(&I.ctl->sweeps_done, (int)(cursor / Mw));
+    atomicMax(&I.ctl->sweeps_done, (int)(cursor / (rnd ? npw : Mw)));
     if (I.wstate) {
       I.wstate[2 * w] = cursor;
       I.wstate[2 * w + 1] = quiet;

@@ -58,6 +58,7 @@ int main(void) {
   printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(dcdl_dict_opts), sizeof(dcdl_dict_info), sizeof(dcdl_cdl_opts),
          sizeof(dcdl_cdl_info), offsetof(dcdl_cdl_opts, dict), offsetof(dcdl_cdl_info, n_updates));
   printf("%zu %zu\\n", sizeof(dcdl_tune_info), offsetof(dcdl_csc_info, beta_drift));
+  printf("%zu %zu %d\\n", offsetof(dcdl_csc_opts, strategy), offsetof(dcdl_csc_opts, seed), (int)DCDL_SELECT_RANDOM);
   return 0;
 }
 """)
@@ -80,6 +81,8 @@ int main(void) {
                    ctypes.sizeof(dl.CdlInfo), dl.CdlOpts.dict.offset, dl.CdlInfo.n_updates.offset]
     last = [int(v) for v in lines[5].split()]
     assert last == [ctypes.sizeof(dl.TuneInfo), dl.CscInfo.beta_drift.offset]
+    sel = [int(v) for v in lines[6].split()]
+    assert sel == [dl.CscOpts.strategy.offset, dl.CscOpts.seed.offset, dl.SELECT["random"]]
 
 
 def test_argument_checks_before_device_access(lib):
@@ -99,6 +102,12 @@ def test_argument_checks_before_device_access(lib):
     rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(o),
                           ctypes.c_void_p(1), ctypes.byref(info), None)
     assert rc == -1 and b"lambda" in lib.dicodile_last_error()
+    o = dl.make_opts(1.0, 0.0, 0, strategy=4)
+    rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(o),
+                          ctypes.c_void_p(1), ctypes.byref(info), None)
+    assert rc == -1 and b"selection rule" in lib.dicodile_last_error()
+    with pytest.raises(dl.DicodileError):
+        dl.make_opts(1.0, 0.0, 0, strategy="sideways")
     # server calls: NULL handles and arguments are rejected before any device access
     assert lib.dicodile_server_create(None, 0, None, None, None) == -1
     assert lib.dicodile_server_submit(None, None, None, None, None, None) == -1
