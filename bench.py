@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="image_1024",
-                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images", "serving", "corr"])
+                    choices=["image_1024", "signal_1d", "image_rgb_4096", "batch_images", "serving", "corr",
+                             "ablation"])
     ap.add_argument("--requests", type=int, default=2000, help="measured requests of the serving workload")
     ap.add_argument("--serve-warmup", type=int, default=200, help="warm-up requests of the serving workload")
     ap.add_argument("--pool", type=int, default=48, help="distinct request signals of the serving workload")
@@ -73,6 +74,8 @@ def parse():
     ap.add_argument("--tile", type=int, nargs="*", default=None)
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--no-autotune", action="store_true", help="batch: skip the autotuner (defaults)")
+    ap.add_argument("--ablation-cap", type=float, default=30.0,
+                    help="ablation: wall-clock cap of one solve in seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=128, help="side of the oracle's crop")
     ap.add_argument("--probe-mib", type=int, default=1024, help="copy-probe size (0: skip)")
@@ -409,10 +412,96 @@ def run_corr_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def _solve_record(dl, torch, pb, cap, **opts):
+    """One timed solve of a synthetic problem (FP32, lambda and tol from its
+    recipe); the library's own clock (t_total_s) covers init, rounds and the
+    FP64 check."""
+    X = torch.from_numpy(pb.X).to("cuda", dtype=torch.float32).contiguous()
+    D = torch.from_numpy(pb.D).to("cuda", dtype=torch.float32).contiguous()
+    lam = pb.lambda_frac * dl.dicodile_lambda_max(X, D)
+    tol = pb.tol_rel * lam
+    try:
+        _, info = dl.dicodile_csc(X, D, lam, tol, max_rounds=1 << 30, timeout_s=cap, **opts)
+    except dl.DicodileError as e:
+        return {"status": str(e).split(":")[0], "opts": {k: v for k, v in opts.items()}}
+    return {"status": info["status"], "t_s": info["t_total_s"], "t_rounds_s": info["t_cd_s"],
+            "updates": info["n_updates"], "rounds": info["n_rounds"], "sweeps": info["n_sweeps"],
+            "softlocked": info["n_softlocked"], "objective": info["objective"], "kkt": info["kkt"],
+            "grid": list(info["grid"]), "tile": list(info["tile"])}
+
+
+def run_ablation(args):
+    """Sec. 5's comparisons re-run on synthetic inputs (the paper's own data
+    for the image experiments is not available):
+      * selection rules with one worker (LGCD, randomized and greedy CD) on the
+        paper's 1-D recipe (P=7, K=25, L=250, T = 150 L and 750 L);
+      * the soft-lock ablation on 512x512 images with 7x7 workers and with
+        workers of about one sub-domain, without the soft-lock test (divergence
+        guard on) and with, for K=25 i.i.d. Gaussian atoms 16x16 and for K=4
+        smooth (strongly overlapping) atoms 10x10;
+      * the line vs grid split of a 512x512 image with K=5 atoms 8x8.
+    Every solve is capped at --ablation-cap seconds of wall clock."""
+    import torch
+    import paper_1901_09235_amd as dl
+    from paper_1901_09235_amd import synth
+    cap = args.ablation_cap
+    _solve_record(dl, torch, synth.paper_signal_1d(T=4000), cap, grid=1)  # warm-up: library set-up
+    res = {"rules_1d": {}, "soft_lock": {}, "split": {"line": {}, "grid": {}}}
+    for mult in (150, 750):
+        pb = synth.paper_signal_1d(T=mult * 250)
+        for rule in ("lgcd", "random", "greedy"):
+            r = _solve_record(dl, torch, pb, cap, grid=1, strategy=rule, seed=1)
+            res["rules_1d"][f"T{mult}L_{rule}"] = r
+            print(f"# rules T={mult}L {rule}: {r}", file=sys.stderr, flush=True)
+        ref = res["rules_1d"][f"T{mult}L_lgcd"].get("objective")
+        for rule in ("random", "greedy"):
+            r = res["rules_1d"][f"T{mult}L_{rule}"]
+            if ref and "objective" in r:
+                r["objective_gap_vs_lgcd"] = (r["objective"] - ref) / abs(ref)
+    import numpy as np
+    for atoms in ("gaussian", "smooth"):
+        if atoms == "smooth":
+            Dab = synth.smooth_dictionary(np.random.Generator(np.random.PCG64(8002)), 4, 1, (10, 10))
+            pb = synth.make_problem("ablation_softlock_512_K4_L10_smooth", 8000, P=1, T=(512, 512), K=4,
+                                    L=(10, 10), rho=0.01, amp="uniform", sigma=0.1, D=Dab)
+        else:
+            pb = synth.make_problem("ablation_softlock_512_K25_L16_gaussian", 8000, P=1, T=(512, 512), K=25,
+                                    L=(16, 16), rho=0.002, amp="uniform", sigma=0.1)
+        # 7x7 workers as in the paper, and workers of about one sub-domain each
+        fine = (25, 25) if atoms == "smooth" else (31, 31)
+        for grid in ((7, 7), fine):
+            for name, kw in (("no_soft_lock", dict(no_soft_lock=True, div_guard=1e3)), ("soft_lock", {})):
+                r = _solve_record(dl, torch, pb, cap, grid=grid, **kw)
+                res["soft_lock"][f"{atoms}_{grid[0]}x{grid[1]}_{name}"] = r
+                print(f"# soft-lock ablation, {atoms} atoms, {grid[0]}x{grid[1]} workers, {name}: {r}",
+                      file=sys.stderr, flush=True)
+    pb = synth.make_problem("ablation_split_512_K5_L8", 8001, P=1, T=(512, 512), K=5, L=(8, 8),
+                            rho=0.002, amp="uniform", sigma=0.1)
+    for w in (1, 2, 4, 8, 16, 32, 63):
+        r = _solve_record(dl, torch, pb, cap, grid=(1, w))
+        res["split"]["line"][w] = r
+        print(f"# line split W={w}: {r}", file=sys.stderr, flush=True)
+    for w in (1, 2, 4, 8, 16, 32):
+        r = _solve_record(dl, torch, pb, cap, grid=(w, w))
+        res["split"]["grid"][w * w] = r
+        print(f"# grid split W={w * w}: {r}", file=sys.stderr, flush=True)
+    head = res["rules_1d"]["T750L_lgcd"]
+    line = {
+        "metric": "time to tolerance of the selection-rule and partition ablations", "value": head.get("t_s"),
+        "unit": "s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": 1e3 * head.get("t_s", float("nan")),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "ablation_rules_T750L_lgcd_1worker", "cap_s": cap},
+        "results": res,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     if args.workload == "corr" and args.gpus == 1:
         return run_corr_bench(args)
+    if args.workload == "ablation" and args.gpus == 1:
+        return run_ablation(args)
     if args.workload == "serving" and args.gpus == 1:
         return run_serving(args)
     if args.workload == "batch_images" and args.gpus == 1:

@@ -59,6 +59,32 @@ def gaussian_dictionary(rng, K: int, P: int, L) -> np.ndarray:
     return D / norms.reshape((K,) + (1,) * (D.ndim - 1))
 
 
+def smooth_dictionary(rng, K: int, P: int, L) -> np.ndarray:
+    """K smooth 2-D atoms of shape L = (L1, L2): an oriented anisotropic
+    Gaussian envelope (widths U(1.5, 5) pixels, angle U(0, pi)) times a
+    low-frequency cosine along its long axis (U(0, 0.6) rad/pixel), the same
+    on every channel up to a N(0,1) channel weight, scaled to unit l2 norm.
+    Shifted copies of such atoms overlap strongly, like the patch-like atoms
+    learnt on natural images; the i.i.d. Gaussian atoms of
+    gaussian_dictionary barely do."""
+    L1, L2 = (int(v) for v in L)
+    yy, xx = np.mgrid[0:L1, 0:L2]
+    yy = yy - (L1 - 1) / 2.0
+    xx = xx - (L2 - 1) / 2.0
+    D = np.empty((K, P, L1, L2))
+    for k in range(K):
+        sx, sy = rng.uniform(1.5, 5.0, size=2)
+        th = rng.uniform(0.0, np.pi)
+        f = rng.uniform(0.0, 0.6)
+        u = np.cos(th) * xx + np.sin(th) * yy
+        v = -np.sin(th) * xx + np.cos(th) * yy
+        atom = np.exp(-0.5 * ((u / sx) ** 2 + (v / sy) ** 2)) * np.cos(f * u)
+        w = rng.standard_normal(P) if P > 1 else np.ones(1)
+        D[k] = w[:, None, None] * atom[None]
+        D[k] /= np.sqrt((D[k] ** 2).sum())
+    return D
+
+
 def bernoulli_support(rng, n: int, rho: float) -> np.ndarray:
     """Indices of a Bernoulli(rho) process on [0, n[, drawn as geometric gaps."""
     if rho <= 0.0 or n == 0:

@@ -137,6 +137,28 @@ def test_no_soft_lock_ablation_with_divergence_guard(lib):
     assert oracle.kkt(pb.X, pb.D, z.cpu().numpy(), lam) <= 1e-4
 
 
+def test_no_soft_lock_diverges_on_coherent_atoms(lib):
+    """The oracle's bulk-synchronous rounds blow up without the soft-lock on
+    smooth atoms (pinned on the CPU); the GPU's rounds do too and stop on the
+    divergence guard, while with the soft-lock they reach the oracle's
+    minimiser."""
+    D = synth.smooth_dictionary(np.random.Generator(np.random.PCG64(80)), 4, 1, (10, 10))
+    pb = synth.make_problem("sl", 81, P=1, T=(56, 56), K=4, L=(10, 10), rho=0.01, amp="uniform",
+                            sigma=0.1, D=D)
+    X, Dd = dev(pb.X, torch.float64), dev(D, torch.float64)
+    lam = 0.1 * oracle.lambda_max(pb.X, D)
+    with pytest.raises(lib.DicodileError) as e:
+        lib.dicodile_csc(X, Dd, lam, 1e-6 * lam, grid=(4, 4), no_soft_lock=True, div_guard=1e4,
+                         max_rounds=200_000, timeout_s=60)
+    assert e.value.code == -4  # EDIVERGED
+    z, info = lib.dicodile_csc(X, Dd, lam, 1e-10 * lam, grid=(4, 4), max_rounds=20_000_000, timeout_s=60)
+    assert info["status"] == "OK"
+    Zo, _ = oracle.lgcd(pb.X, D, lam, 1e-8 * lam)
+    fo = oracle.objective(pb.X, D, Zo, lam)
+    assert (oracle.objective(pb.X, D, z.cpu().numpy(), lam) - fo) / fo <= 1e-6
+    assert oracle.kkt(pb.X, D, z.cpu().numpy(), lam) <= 1e-4
+
+
 def test_rule_errors(lib):
     pb = _signal(107)
     X, D = dev(pb.X, torch.float32), dev(pb.D, torch.float32)

@@ -14,6 +14,7 @@ from scipy import signal, stats
 
 import oracle
 from oracle import brute
+from paper_1901_09235_amd import synth
 
 
 def _rng(seed):
@@ -177,3 +178,29 @@ def test_cyclic_first_position_takes_its_best_atom():
     k = int(np.argmax(np.abs(T0[:, 0, 0])))
     assert Z[k, 0, 0] == pytest.approx(T0[k, 0, 0], rel=1e-12)
     assert np.count_nonzero(Z[:, 0, 0]) == 1
+
+
+# ------------------------------------------------------------ soft-lock ablation
+
+def test_without_soft_lock_coherent_atoms_diverge():
+    """Sec. 5's soft-lock ablation: with strongly overlapping (smooth) atoms,
+    applying every worker's candidate of a round together blows up, while the
+    soft-lock rounds apply no interacting pair and reach the sequential
+    minimiser.  With i.i.d. Gaussian atoms the same unlocked rounds still
+    converge."""
+    D = synth.smooth_dictionary(_rng(80), 4, 1, (10, 10))
+    pb = synth.make_problem("sl", 81, P=1, T=(56, 56), K=4, L=(10, 10), rho=0.01, amp="uniform",
+                            sigma=0.1, D=D)
+    lam = 0.1 * oracle.lambda_max(pb.X, D)
+    _, info, _ = oracle.dicodile_z(pb.X, D, lam, 1e-6 * lam, grid=(4, 4), soft_lock=False,
+                                   div_guard=1e4, max_rounds=2000)
+    assert info["diverged"] == 1 and info["n_interfering"] > 0
+    Z, info, _ = oracle.dicodile_z(pb.X, D, lam, 1e-5 * lam, grid=(4, 4), max_rounds=400000)
+    assert info["converged"] == 1 and info["n_interfering"] == 0
+    Zl, _ = oracle.lgcd(pb.X, D, lam, 1e-5 * lam)
+    assert oracle.objective(pb.X, D, Z, lam) == pytest.approx(oracle.objective(pb.X, D, Zl, lam), rel=1e-8)
+    pg = synth.make_problem("sg", 82, P=1, T=(56, 56), K=4, L=(10, 10), rho=0.01, amp="uniform", sigma=0.1)
+    lam = 0.1 * oracle.lambda_max(pg.X, pg.D)
+    _, info, _ = oracle.dicodile_z(pg.X, pg.D, lam, 1e-6 * lam, grid=(4, 4), soft_lock=False,
+                                   div_guard=1e4, max_rounds=400000)
+    assert info["converged"] == 1 and info["diverged"] == 0
