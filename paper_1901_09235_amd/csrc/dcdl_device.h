@@ -292,9 +292,17 @@ __device__ __forceinline__ int block_or(int v, int *sh) {
 
 // ------------------------------------------------------------- the round kernel
 
+// Items (position, atom group) one LDS block of a patch holds: 28 KB of
+// staging for FP32 and FP64 alike, so that four FP32 or three FP64 workers
+// share a CU.
+template <class R> struct PatchBuf {
+  static constexpr int N = sizeof(R) == 4 ? 4096 : 2048;
+};
+
 template <class R, int NT> struct PatchCtx {
   R *sh_ps;
   uint16_t *sh_pk;
+  uint16_t *sh_nz;  // non-zero counts of a block's positions (patch_union)
   const R *sh_inv_n;
   int G, spl, sq, pl0, q0;
 };
@@ -307,7 +315,7 @@ template <class R, int NT> struct PatchCtx {
 template <class R, int NT>
 __device__ __forceinline__ void patch_region(const Inst<R> &I, const PatchCtx<R, NT> &P, int r1, int r2, int c1,
                                              int c2, int ck, int ch, int cw0, R delta) {
-  constexpr int LBUF = 4096;
+  constexpr int LBUF = PatchBuf<R>::N;
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
   const int tid = threadIdx.x;
@@ -402,15 +410,86 @@ template <class R> struct UCand {
 // once.  Positions no update covers are left untouched.  The sum runs over
 // the updates in increasing worker order, as applying them one after another
 // would.  Every thread of the workgroup takes part.
+//
+// The box is cut into blocks of at most LBUF (position, atom group) items.  A
+// block first stages its positions' non-zero counts in LDS, so that the z
+// read of an item is issued together with its beta and DtD reads; the items
+// then run two per thread and pass, every load of both in flight before either
+// is used.  Their per-group best moves meet in LDS, and a last pass reduces
+// them per position into the score and meta caches.
+template <class R> struct PItem {
+  typename Vec<R>::T b, a, z;
+  int t, q, rr, cc;
+  unsigned m;  // updates covering the item's position, the first one's DtD row in a
+};
+
+template <class R, int NT>
+__device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int nc,
+                                           int it, int nit, int rr0, int cc0, int ccw, int rowstride, PItem<R> &x) {
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  x.m = 0;
+  if (it >= nit) return;
+  const int G = P.G;
+  x.t = it / G;
+  x.q = it - x.t * G;
+  const int tr = x.t / ccw;
+  x.rr = rr0 + tr;
+  x.cc = cc0 + (x.t - tr * ccw);
+  for (int c = 0; c < nc; ++c)
+    if (x.rr >= uc[c].r1 && x.rr < uc[c].r2 && x.cc >= uc[c].c1 && x.cc < uc[c].c2) x.m |= 1u << c;
+  if (!x.m) return;
+  const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE;
+  x.b = *reinterpret_cast<const V *>(I.beta + e);
+  x.a = *reinterpret_cast<const V *>(I.A + (uc[__ffs(x.m) - 1].aoff + x.rr * rowstride + x.cc * I.KS + x.q * VE));
+  x.z = P.sh_nz[x.t] ? *reinterpret_cast<const V *>(I.z + e) : Vec<R>::zero();
+}
+
+template <class R, int NT>
+__device__ __forceinline__ void pitem_apply(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int it,
+                                            int rowstride, PItem<R> &x) {
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  if (!x.m) return;
+  V b = x.b;
+  unsigned m = x.m;
+  bool first = true;
+  while (m) {
+    const int c = __ffs(m) - 1;
+    m &= m - 1;
+    const UCand<R> &u = uc[c];
+    const V av = first ? x.a
+                       : *reinterpret_cast<const V *>(I.A + (u.aoff + x.rr * rowstride + x.cc * I.KS + x.q * VE));
+    first = false;
+    const V bold = b;
+    b = Vec<R>::fma_neg(b, av, u.delta);
+    if (x.rr == u.ch && x.cc == u.cw0 && x.q == u.k0 / VE)
+      Vec<R>::set(b, u.k0 % VE, Vec<R>::get(bold, u.k0 % VE));  // the updated coordinate itself
+  }
+  *reinterpret_cast<V *>(I.beta + ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE) = b;
+  R best = R(-1);
+  int bk = 0;
+#pragma unroll
+  for (int e = 0; e < VE; ++e) {
+    const int k = x.q * VE + e;
+    const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
+    const R sc = k < I.K ? move_score(Vec<R>::get(x.z, e), zn, I.tol, I.certify) : R(-1);
+    if (sc > best) {
+      best = sc;
+      bk = k;
+    }
+  }
+  P.sh_ps[it] = best;
+  P.sh_pk[it] = (uint16_t)bk;
+}
+
 template <class R, int NT>
 __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int nc,
                                             int R1, int R2, int C1, int C2) {
-  constexpr int LBUF = 4096;
-  typedef typename Vec<R>::T V;
-  constexpr int VE = Vec<R>::N;
+  constexpr int LBUF = PatchBuf<R>::N;
   const int tid = threadIdx.x;
-  const int K = I.K, KS = I.KS, W = I.W, G = P.G;
-  const int rowstride = I.U2 * KS;
+  const int W = I.W, G = P.G;
+  const int rowstride = I.U2 * I.KS;
   const int ncol = C2 - C1;
   const int cw = min(ncol, LBUF / G);
   const int rc = max(1, LBUF / (cw * G));
@@ -418,79 +497,29 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
     const int rr1 = min(rr0 + rc, R2);
     for (int cc0 = C1; cc0 < C2; cc0 += cw) {
       const int ccw = min(cw, C2 - cc0);
-      const int ng = ccw * G;
-      for (int rr = rr0; rr < rr1; ++rr) {
-        R *prow = P.sh_ps + (rr - rr0) * ng;
-        uint16_t *krow = P.sh_pk + (rr - rr0) * ng;
-        unsigned rm = 0;  // updates whose patch covers row rr
-        for (int c = 0; c < nc; ++c)
-          if (rr >= uc[c].r1 && rr < uc[c].r2) rm |= 1u << c;
-        if (!rm) {
-          for (int j = tid; j < ng; j += NT) prow[j] = R(-2);
-          continue;
-        }
-        V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
-        const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
-        const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
-        const int arow = rr * rowstride;
-        int pl = P.pl0, qq = P.q0;
-#pragma unroll 1
-        for (int j = tid; j < ng; j += NT) {
-          const int cc = cc0 + pl;
-          V b = Vec<R>::zero();
-          bool any = false;
-          unsigned m = rm;
-          while (m) {
-            const int c = __ffs(m) - 1;
-            m &= m - 1;
-            const UCand<R> &u = uc[c];
-            if (cc < u.c1 || cc >= u.c2) continue;
-            if (!any) {
-              b = brow[j];
-              any = true;
-            }
-            const V av = *reinterpret_cast<const V *>(I.A + (u.aoff + arow + cc * KS + qq * VE));
-            const V bold = b;
-            b = Vec<R>::fma_neg(b, av, u.delta);
-            if (rr == u.ch && cc == u.cw0 && qq == u.k0 / VE)
-              Vec<R>::set(b, u.k0 % VE, Vec<R>::get(bold, u.k0 % VE));  // the updated coordinate itself
-          }
-          if (any) {
-            brow[j] = b;
-            const uint32_t mt = mrow[pl];
-            const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
-            R best = R(-1);
-            int bk = 0;
-#pragma unroll
-            for (int e = 0; e < VE; ++e) {
-              const int k = qq * VE + e;
-              const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
-              const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
-              if (sc > best) {
-                best = sc;
-                bk = k;
-              }
-            }
-            prow[j] = best;
-            krow[j] = (uint16_t)bk;
-          } else {
-            prow[j] = R(-2);  // no update covers this position: its cache stays
-          }
-          qq += P.sq;
-          pl += P.spl;
-          if (qq >= G) {
-            qq -= G;
-            pl += 1;
-          }
-        }
+      const int npos = (rr1 - rr0) * ccw;
+      for (int t = tid; t < npos; t += NT) {
+        const int tr = t / ccw;
+        P.sh_nz[t] = (uint16_t)meta_nzc(I.meta[(long long)(rr0 + tr) * W + cc0 + (t - tr * ccw)]);
       }
       __syncthreads();
-      const int npos = (rr1 - rr0) * ccw;
+      const int nit = npos * G;
+#pragma unroll 1
+      for (int i0 = tid; i0 < nit; i0 += 2 * NT) {
+        PItem<R> x0, x1;
+        pitem_load<R, NT>(I, P, uc, nc, i0, nit, rr0, cc0, ccw, rowstride, x0);
+        pitem_load<R, NT>(I, P, uc, nc, i0 + NT, nit, rr0, cc0, ccw, rowstride, x1);
+        if (i0 < nit && !x0.m) P.sh_ps[i0] = R(-2);  // no update covers this position: its cache stays
+        if (i0 + NT < nit && !x1.m) P.sh_ps[i0 + NT] = R(-2);
+        pitem_apply<R, NT>(I, P, uc, i0, rowstride, x0);
+        pitem_apply<R, NT>(I, P, uc, i0 + NT, rowstride, x1);
+      }
+      __syncthreads();
       for (int t = tid; t < npos; t += NT) {
         const R *pp = P.sh_ps + t * G;
         if (pp[0] == R(-2)) continue;
-        const int rr = rr0 + t / ccw, pl = t % ccw;
-        const int pos = rr * W + cc0 + pl;
+        const int tr = t / ccw;
+        const int pos = (rr0 + tr) * W + cc0 + (t - tr * ccw);
         const uint16_t *pk = P.sh_pk + t * G;
         R best = pp[0];
         int bk = pk[0];
@@ -500,7 +529,7 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
             bk = pk[g];
           }
         score_st(I.score + pos, best);
-        I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
+        I.meta[pos] = meta_pack(bk, P.sh_nz[t]);
       }
       __syncthreads();
     }
@@ -542,9 +571,10 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
 // the soft-lock test still rejects at least one: each sees the other's
 // position holding a score >= its own (ties go to the lower worker index).
 template <class R, int NT> struct RoundSmem {
-  static constexpr int LBUF = 4096;
+  static constexpr int LBUF = PatchBuf<R>::N;
   R ps[LBUF];
   uint16_t pk[LBUF];
+  uint16_t nz[LBUF];
   R inv_n[1024];
   R rs[NT / 64];
   int ri[NT / 64];
@@ -597,6 +627,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   PatchCtx<R, NT> P;
   P.sh_ps = sm.ps;
   P.sh_pk = sm.pk;
+  P.sh_nz = sm.nz;
   P.sh_inv_n = sh_inv_n;
   P.G = I.KS / VE;
   P.spl = NT / P.G;
@@ -980,8 +1011,14 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   }
 }
 
+// Four 256-thread FP32 workers per CU (at most 128 VGPRs): the co-resident
+// worker count sets how finely an image can be split.
+template <class R, int NT> struct RoundWaves {
+  static constexpr int value = sizeof(R) == 4 ? (NT <= 256 ? NT / 64 : 4) : 1;
+};
+
 template <class R, int NT>
-__global__ __launch_bounds__(NT) void lgcd_rounds(const Inst<R> *__restrict__ insts,
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(RoundWaves<R, NT>::value))) void lgcd_rounds(const Inst<R> *__restrict__ insts,
                                                    const int *__restrict__ wg_inst,
                                                    long long timeout_ticks) {
   __shared__ RoundSmem<R, NT> sm;
