@@ -307,92 +307,6 @@ template <class R, int NT> struct PatchCtx {
   int G, spl, sq, pl0, q0;
 };
 
-// Applies one accepted update (atom ck at position (ch, cw0), change delta) to
-// rows [r1, r2) x columns [c1, c2) of this worker's region: beta -= A * delta
-// (eq. beta_update; beta at the updated coordinate itself is unchanged), then
-// recomputes the best-move cache of the patched positions.  Every thread of
-// the workgroup takes part; the region must lie inside the worker's domain.
-template <class R, int NT>
-__device__ __forceinline__ void patch_region(const Inst<R> &I, const PatchCtx<R, NT> &P, int r1, int r2, int c1,
-                                             int c2, int ck, int ch, int cw0, R delta) {
-  constexpr int LBUF = PatchBuf<R>::N;
-  typedef typename Vec<R>::T V;
-  constexpr int VE = Vec<R>::N;
-  const int tid = threadIdx.x;
-  const int K = I.K, KS = I.KS, W = I.W, G = P.G;
-  const int nc = c2 - c1;
-  const int cw = min(nc, LBUF / G);
-  const int rc = max(1, LBUF / (cw * G));
-  const int cg = ck / VE, ce = ck - cg * VE;
-  for (int rr0 = r1; rr0 < r2; rr0 += rc) {
-    const int rr1 = min(rr0 + rc, r2);
-    for (int cc0 = c1; cc0 < c2; cc0 += cw) {
-      const int ccw = min(cw, c2 - cc0);
-      const int ng = ccw * G;
-      for (int rr = rr0; rr < rr1; ++rr) {
-        V *__restrict__ brow = reinterpret_cast<V *>(I.beta + ((long long)rr * W + cc0) * KS);
-        const V *__restrict__ arow = reinterpret_cast<const V *>(
-            I.A + (((long long)ck * I.U1 + (rr - ch + I.L1 - 1)) * I.U2 + (cc0 - cw0 + I.L2 - 1)) * KS);
-        const V *__restrict__ zrow = reinterpret_cast<const V *>(I.z + ((long long)rr * W + cc0) * KS);
-        const uint32_t *__restrict__ mrow = I.meta + (long long)rr * W + cc0;
-        const int gself = (rr == ch && cw0 >= cc0 && cw0 < cc0 + ccw) ? (cw0 - cc0) * G + cg : -1;
-        R *prow = P.sh_ps + (rr - rr0) * ng;
-        uint16_t *krow = P.sh_pk + (rr - rr0) * ng;
-        int pl = P.pl0, qq = P.q0;
-#pragma unroll 4
-        for (int j = tid; j < ng; j += NT) {
-          V b = brow[j];
-          const V av = arow[j];
-          const uint32_t mt = mrow[pl];
-          const V bold = b;
-          b = Vec<R>::fma_neg(b, av, delta);
-          if (j == gself) Vec<R>::set(b, ce, Vec<R>::get(bold, ce));  // beta at (k0, w0) is unchanged
-          brow[j] = b;
-          const V zv = meta_nzc(mt) ? zrow[j] : Vec<R>::zero();
-          R best = R(-1);
-          int bk = 0;
-#pragma unroll
-          for (int e = 0; e < VE; ++e) {
-            const int k = qq * VE + e;
-            const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
-            const R sc = k < K ? move_score(Vec<R>::get(zv, e), zn, I.tol, I.certify) : R(-1);
-            if (sc > best) {
-              best = sc;
-              bk = k;
-            }
-          }
-          prow[j] = best;
-          krow[j] = (uint16_t)bk;
-          qq += P.sq;
-          pl += P.spl;
-          if (qq >= G) {
-            qq -= G;
-            pl += 1;
-          }
-        }
-      }
-      __syncthreads();
-      const int npos = (rr1 - rr0) * ccw;
-      for (int t = tid; t < npos; t += NT) {
-        const int rr = rr0 + t / ccw, pl = t % ccw;
-        const int pos = rr * W + cc0 + pl;
-        const R *pp = P.sh_ps + t * G;
-        const uint16_t *pk = P.sh_pk + t * G;
-        R best = pp[0];
-        int bk = pk[0];
-        for (int g = 1; g < G; ++g)
-          if (pp[g] > best) {
-            best = pp[g];
-            bk = pk[g];
-          }
-        score_st(I.score + pos, best);
-        I.meta[pos] = meta_pack(bk, meta_nzc(I.meta[pos]));
-      }
-      __syncthreads();
-    }
-  }
-}
-
 // An accepted update as the apply phase uses it: atom k0 at (ch, cw0), change
 // delta, and the rows [r1, r2) x columns [c1, c2) of this worker's region it
 // patches.
@@ -578,8 +492,8 @@ template <class R, int NT> struct RoundSmem {
   R inv_n[1024];
   R rs[NT / 64];
   int ri[NT / 64];
-  int exit_f, wait_f, cok, k0;
-  R d;
+  int exit_f, wait_f, cok;
+  UCand<R> ui;  // an interior candidate applied within phase A
   unsigned long long tag[9];
   R delta[9];
   int nbr[9];
@@ -599,8 +513,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   int &sh_exit = sm.exit_f;
   int &sh_wait = sm.wait_f;
   int &sh_cok = sm.cok;
-  int &sh_k0 = sm.k0;
-  R &sh_d = sm.d;
   unsigned long long *const sh_tag = sm.tag;
   R *const sh_delta = sm.delta;
   int *const sh_nbr = sm.nbr;
@@ -783,8 +695,16 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
         I.z[i0] = zn;
         const uint32_t mt = I.meta[vp];
         I.meta[vp] = meta_pack(meta_argk(mt), meta_nzc(mt) + (zn != R(0)) - (zc != R(0)));
-        sh_k0 = k0;
-        sh_d = zn - zc;
+        UCand<R> &u = sm.ui;
+        u.k0 = k0;
+        u.ch = h0;
+        u.cw0 = w0;
+        u.r1 = max(h0 - I.L1 + 1, a1);
+        u.r2 = min(h0 + I.L1, b1);
+        u.c1 = max(w0 - I.L2 + 1, a2);
+        u.c2 = min(w0 + I.L2, b2);
+        u.aoff = ((k0 * I.U1 - h0 + I.L1 - 1) * I.U2 - w0 + I.L2 - 1) * I.KS;
+        u.delta = zn - zc;
         if (I.div_guard > R(0) && (zn > I.div_guard || -zn > I.div_guard)) {
           st_shared_i32(&I.ctl->stop, 1);
           atomicCAS(&I.ctl->status, 0, 2);
@@ -793,10 +713,8 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       }
       __syncthreads();
       ++my_upd;
-      my_patch += (unsigned long long)(min(h0 + I.L1, b1) - max(h0 - I.L1 + 1, a1)) *
-                  (min(w0 + I.L2, b2) - max(w0 - I.L2 + 1, a2));
-      patch_region<R, NT>(I, P, max(h0 - I.L1 + 1, a1), min(h0 + I.L1, b1), max(w0 - I.L2 + 1, a2),
-                          min(w0 + I.L2, b2), sh_k0, h0, w0, sh_d);
+      my_patch += (unsigned long long)(sm.ui.r2 - sm.ui.r1) * (sm.ui.c2 - sm.ui.c1);
+      patch_union<R, NT>(I, P, &sm.ui, 1, sm.ui.r1, sm.ui.r2, sm.ui.c1, sm.ui.c2);
     }
     if (restart >= 0) cursor = restart;
     int h0 = 0, w0 = 0;
@@ -945,10 +863,8 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       if (sm.ub_union || sm.nuc == 1) {
         patch_union<R, NT>(I, P, sm.uc, sm.nuc, sm.ub[0], sm.ub[1], sm.ub[2], sm.ub[3]);
       } else {
-        for (int c = 0; c < sm.nuc; ++c) {
-          const UCand<R> &u = sm.uc[c];
-          patch_region<R, NT>(I, P, u.r1, u.r2, u.c1, u.c2, u.k0, u.ch, u.cw0, u.delta);
-        }
+        for (int c = 0; c < sm.nuc; ++c)
+          patch_union<R, NT>(I, P, sm.uc + c, 1, sm.uc[c].r1, sm.uc[c].r2, sm.uc[c].c1, sm.uc[c].c2);
       }
     }
     // cache stores complete before the progress counter moves
