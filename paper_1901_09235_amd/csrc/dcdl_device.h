@@ -58,8 +58,9 @@ __host__ __device__ inline int atom_stride(int K, int elem_bytes) {
   return (K + ve - 1) / ve * ve;
 }
 
-// Per-instance control block, followed in memory by two rings of kRing ints
-// (per-round completion counts and per-round quiet counts).
+// Per-instance control block, followed in memory by a ring of kRing 64-bit
+// per-round counters (completions in the low word, quiet workers in the high
+// word).
 struct Ctl {
   int32_t converged;
   int32_t stop;
@@ -94,7 +95,7 @@ template <class R> struct Inst {
   unsigned long long *cand;  // 2 words per worker
   int *prog;
   Ctl *ctl;
-  int *ring;  // done[kRing] then active[kRing]
+  int *ring;  // kRing 64-bit slots: completions (low word) and quiet workers (high word) of a round
   // optional, 2 per worker: visits so far and the quiet count, loaded at the
   // start of a launch and stored at its end, so that a solve split over
   // several launches (each capped by max_rounds) keeps its stopping state
@@ -104,9 +105,13 @@ template <class R> struct Inst {
 // ----------------------------------------------------------------- arithmetic
 
 // Closed-form coordinate target of eq. pb_coord: ST(b, lambda) / ||D_k||^2,
-// one-sided when positive.
+// one-sided when positive.  The product is rounded on its own (no
+// contraction into a later subtraction): the move score |zn - z| must be that
+// of the value z takes, or a coordinate at its target keeps a score of the
+// size of zn's rounding error and a tolerance below it is never certified.
 template <class R>
 __device__ __forceinline__ R st_target(R b, R lam, R inv_n, int positive) {
+#pragma clang fp contract(off)
   R u;
   if (positive)
     u = b > lam ? b - lam : R(0);
@@ -302,9 +307,9 @@ template <class R> struct PatchBuf {
 template <class R, int NT> struct PatchCtx {
   R *sh_ps;
   uint16_t *sh_pk;
-  uint16_t *sh_nz;  // non-zero counts of a block's positions (patch_union)
+  uint16_t *sh_nz;  // non-zero counts of a block's positions
   const R *sh_inv_n;
-  int G, spl, sq, pl0, q0;
+  int G;  // 16-byte atom groups per position
 };
 
 // An accepted update as the apply phase uses it: atom k0 at (ch, cw0), change
@@ -542,10 +547,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   P.sh_nz = sm.nz;
   P.sh_inv_n = sh_inv_n;
   P.G = I.KS / VE;
-  P.spl = NT / P.G;
-  P.sq = NT - P.spl * P.G;
-  P.pl0 = tid / P.G;
-  P.q0 = tid - P.pl0 * P.G;
 
   __syncthreads();
   for (int k = tid; k < I.KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
@@ -574,10 +575,11 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   const unsigned long long t_launch = __builtin_amdgcn_s_memrealtime();
   int r = 0;
   int exit_status = 0;
+  int next_exit = 0;  // thread 0: exit flags read at the end of the previous round
   for (;; ++r) {
     // ---- exit conditions
     if (tid == 0) {
-      int f = ld_shared_i32(&I.ctl->converged) | ld_shared_i32(&I.ctl->stop);
+      int f = r == 0 ? (ld_shared_i32(&I.ctl->converged) | ld_shared_i32(&I.ctl->stop)) : next_exit;
       // every worker runs exactly max_rounds rounds: all moves of the last
       // round are then applied everywhere and the launch can be resumed
       if (!f && I.max_rounds > 0 && r >= I.max_rounds) {
@@ -848,14 +850,11 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       sm.ub[2] = v1;
       sm.ub[3] = v2;
       // One pass over the bounding box pays for small patches, whose cost is
-      // mostly per-update latency, when they fill at least half of it.  Large
-      // patches (over 1024 positions) are bandwidth-bound and go one by one:
-      // measured on 16x16 atoms (961-position patches) the pass saves 13% of
-      // the rounds' time, on 32x32 atoms (3969) it costs 7-20%.
-      long long area = 0;
-      for (int c = 0; c < nu; ++c)
-        area += (long long)(sm.uc[c].r2 - sm.uc[c].r1) * (sm.uc[c].c2 - sm.uc[c].c1);
-      sm.ub_union = nu > 1 && (long long)I.U1 * I.U2 <= 1024 && (long long)(u2 - u1) * (v2 - v1) <= area * 2;
+      // mostly per-update latency (positions no update covers cost no loads).
+      // Large patches (over 1024 positions) are bandwidth-bound and go one by
+      // one: measured on 32x32 atoms (3969-position patches) the single pass
+      // costs 15-20% of the rounds' time.
+      sm.ub_union = nu > 1 && (long long)I.U1 * I.U2 <= 1024;
     }
     __syncthreads();
     if (sm.nuc > 0) {
@@ -885,18 +884,25 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     if (tid == 0) {
       st_shared_i32(I.prog + w, r + 1);
       tk_app += __builtin_amdgcn_s_memrealtime() - tk_mark;
-      // ---- stopping consensus: quiet counts of round r
+      // ---- stopping consensus of round r: one 64-bit counter per ring slot,
+      // completions in the low word and quiet workers in the high word.  The
+      // exit flags for the next round are read while the add is in flight; a
+      // flag raised later in this round is seen one round later, which only
+      // costs an empty round.
       const int slot = r % kRing;
-      int *done = I.ring, *qcount = I.ring + kRing;
-      if (quiet >= qthr) __hip_atomic_fetch_add(&qcount[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      wait_vm();
-      const int old = __hip_atomic_fetch_add(&done[slot], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (old == nW - 1) {
-        const int nq = ld_shared_i32(&qcount[slot]);
-        st_shared_i32(&qcount[slot], 0);
-        st_shared_i32(&done[slot], 0);
-        if (nq == nW) st_shared_i32(&I.ctl->converged, 1);
+      unsigned long long *ring = reinterpret_cast<unsigned long long *>(I.ring);
+      const unsigned long long q = quiet >= qthr ? 1ull : 0ull;
+      const unsigned long long old =
+          __hip_atomic_fetch_add(&ring[slot], 1ull + (q << 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int f = ld_shared_i32(&I.ctl->converged) | ld_shared_i32(&I.ctl->stop);
+      if ((old & 0xffffffffull) == (unsigned long long)(nW - 1)) {
+        st_shared_u64(&ring[slot], 0ull);
+        if ((old >> 32) + q == (unsigned long long)nW) {
+          st_shared_i32(&I.ctl->converged, 1);
+          f = 1;
+        }
       }
+      next_exit = f;
     }
   }
   // ---- leave: neighbours must never wait on a finished worker
