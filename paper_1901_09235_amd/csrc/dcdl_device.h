@@ -226,14 +226,16 @@ template <> __device__ __forceinline__ double bits_delta<double>(unsigned long l
 
 // Progress counters of the workers in `nbr` must reach `target`.  Returns
 // false after `timeout_ticks` of the 100 MHz clock.
-__device__ __forceinline__ bool wait_progress(const int *prog, const int *nbr, int nn, int self, int target,
-                                              long long timeout_ticks, int *sh_flag) {
-  if (threadIdx.x == 0) {
+__device__ __forceinline__ bool wait_progress(const int *prog, const int *sh_nbr, int nn, int self, int target,
+                                              long long timeout_ticks, int *sh_ok) {
+  // lanes 0..nn-1 of the first wave each watch one neighbour, so the polls of
+  // all neighbours are in flight together
+  const int q = threadIdx.x;
+  if (q < nn) {
     int ok = 1;
-    const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
-    for (int q = 0; q < nn && ok; ++q) {
-      const int n = nbr[q];
-      if (n == self) continue;
+    const int n = sh_nbr[q];
+    if (n != self) {
+      const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
       while (ld_shared_i32(prog + n) < target) {
         __builtin_amdgcn_s_sleep(1);
         if ((long long)(__builtin_amdgcn_s_memrealtime() - t0) > timeout_ticks) {
@@ -242,10 +244,12 @@ __device__ __forceinline__ bool wait_progress(const int *prog, const int *nbr, i
         }
       }
     }
-    *sh_flag = ok;
+    sh_ok[q] = ok;
   }
   __syncthreads();
-  return *sh_flag != 0;
+  int ok = 1;
+  for (int k = 0; k < nn; ++k) ok &= sh_ok[k];
+  return ok != 0;
 }
 
 // ------------------------------------------------------------ block reductions
@@ -497,7 +501,10 @@ template <class R, int NT> struct RoundSmem {
   R inv_n[1024];
   R rs[NT / 64];
   int ri[NT / 64];
-  int exit_f, wait_f, cok;
+  int exit_f, cok;
+  int wok[9];  // per-neighbour result of the progress wait
+  int ck0;       // the held candidate's atom, current value and target
+  R czc, czn;
   UCand<R> ui;  // an interior candidate applied within phase A
   unsigned long long tag[9];
   R delta[9];
@@ -516,7 +523,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   R *const sh_rs = sm.rs;
   int *const sh_ri = sm.ri;
   int &sh_exit = sm.exit_f;
-  int &sh_wait = sm.wait_f;
   int &sh_cok = sm.cok;
   unsigned long long *const sh_tag = sm.tag;
   R *const sh_delta = sm.delta;
@@ -560,13 +566,9 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     for (int q = nn; q < 9; ++q) sh_nbr[q] = -1;
   }
   __syncthreads();
-  int nbr[9];
   int nn = 0;
 #pragma unroll
-  for (int q = 0; q < 9; ++q) {
-    nbr[q] = sh_nbr[q];
-    nn += nbr[q] >= 0;
-  }
+  for (int q = 0; q < 9; ++q) nn += sh_nbr[q] >= 0;
 
   unsigned long long my_upd = 0, my_cand = 0, my_lock = 0, my_visit = 0, my_chk = 0, my_patch = 0;
   unsigned long long tk_wait = 0, tk_sel = 0, tk_col = 0, tk_app = 0, tk_mark = 0;
@@ -597,15 +599,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     }
     __syncthreads();
     if (sh_exit) break;
-    if (!wait_progress(I.prog, nbr, nn, w, r, timeout_ticks, &sh_wait)) {
-      exit_status = 3;
-      break;
-    }
-    if (tid == 0) {
-      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
-      tk_wait += t - tk_mark;
-      tk_mark = t;
-    }
 
     // ---- phase A: `inner` visits.  Interior candidates are applied at once;
     // the first band-reaching candidate is held for the protocol, and later
@@ -724,6 +717,32 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       h0 = bp / W;
       w0 = bp - h0 * W;
     }
+    // The visits above read only S_w, which this worker alone writes and
+    // finished patching in its last phase B; so do the candidate's reads
+    // below.  Only the soft-lock test (the neighbours' scores of round r - 1)
+    // and the reuse of the candidate slot (read by the neighbours in round
+    // r - 1) need the neighbours' progress.
+    if (tid == 0) {
+      if (has) {
+        const int k0 = rnd ? bk : meta_argk(I.meta[bp]);
+        const long long i0 = (long long)bp * I.KS + k0;
+        sm.ck0 = k0;
+        sm.czc = I.z[i0];
+        sm.czn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+      }
+      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+      tk_sel += t - tk_mark;
+      tk_mark = t;
+    }
+    if (!wait_progress(I.prog, sh_nbr, nn, w, r, timeout_ticks, sm.wok)) {
+      exit_status = 3;
+      break;
+    }
+    if (tid == 0) {
+      const unsigned long long t = __builtin_amdgcn_s_memrealtime();
+      tk_wait += t - tk_mark;
+      tk_mark = t;
+    }
     int locked = 0;
     if (has && I.soft_lock &&
         (h0 - I.L1 + 1 < a1 || h0 + I.L1 > b1 || w0 - I.L2 + 1 < a2 || w0 + I.L2 > b2)) {
@@ -756,10 +775,10 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
         if (locked) {
           ++my_lock;
         } else {
-          const int k0 = rnd ? bk : meta_argk(I.meta[bp]);
+          const int k0 = sm.ck0;
           const long long i0 = (long long)bp * I.KS + k0;
-          const R zc = I.z[i0];
-          const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+          const R zc = sm.czc;
+          const R zn = sm.czn;
           // z and its non-zero count change now; beta and the cache in phase B
           I.z[i0] = zn;
           const uint32_t mt = I.meta[bp];
@@ -783,7 +802,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
 
     // ---- collect this round's candidates of the 3x3 neighbourhood
     if (tid < nn) {
-      const int n = nbr[tid];
+      const int n = sh_nbr[tid];
       unsigned long long t = 0;
       int ok = 1;
       const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
