@@ -301,20 +301,33 @@ __device__ __forceinline__ int block_or(int v, int *sh) {
 
 // ------------------------------------------------------------- the round kernel
 
-// Items (position, atom group) one LDS block of a patch holds: 28 KB of
-// staging for FP32 and FP64 alike, so that four FP32 or three FP64 workers
-// share a CU.
+// Items (position, atom group) one LDS block of a patch holds: 24 KB of
+// staging for FP32 and 20 KB for FP64, so that four FP32 or three FP64
+// workers share a CU.
 template <class R> struct PatchBuf {
   static constexpr int N = sizeof(R) == 4 ? 4096 : 2048;
 };
 
+// Words of the LDS bitmask that marks the positions of S_w holding a non-zero
+// coordinate (workers of up to 32 * kNzWords positions keep one).
+constexpr int kNzWords = 1024;
+
 template <class R, int NT> struct PatchCtx {
   R *sh_ps;
   uint16_t *sh_pk;
-  uint16_t *sh_nz;  // non-zero counts of a block's positions
   const R *sh_inv_n;
-  int G;  // 16-byte atom groups per position
+  uint32_t *nzb;    // bit (h - a1) * ext2 + (w - a2) set when position (h, w) of S_w has a non-zero;
+                    // null for larger workers, whose patches read z everywhere
+  int G;            // 16-byte atom groups per position
+  int a1, a2, ext2;  // origin and width of S_w
 };
+
+__device__ __forceinline__ void nzb_put(uint32_t *nzb, int t, bool on) {
+  if (on)
+    nzb[t >> 5] |= 1u << (t & 31);
+  else
+    nzb[t >> 5] &= ~(1u << (t & 31));
+}
 
 // An accepted update as the apply phase uses it: atom k0 at (ch, cw0), change
 // delta, and the rows [r1, r2) x columns [c1, c2) of this worker's region it
@@ -334,12 +347,12 @@ template <class R> struct UCand {
 // the updates in increasing worker order, as applying them one after another
 // would.  Every thread of the workgroup takes part.
 //
-// The box is cut into blocks of at most LBUF (position, atom group) items.  A
-// block first stages its positions' non-zero counts in LDS, so that the z
-// read of an item is issued together with its beta and DtD reads; the items
-// then run two per thread and pass, every load of both in flight before either
-// is used.  Their per-group best moves meet in LDS, and a last pass reduces
-// them per position into the score and meta caches.
+// The box is cut into blocks of at most LBUF (position, atom group) items,
+// run two per thread and pass with every load of both in flight before either
+// is used: beta, the DtD row and, where the worker's LDS bitmask marks a
+// non-zero coordinate, z.  Their per-group best moves meet in LDS, and a last
+// pass reduces them per position into the score cache and the atom half of
+// meta.
 template <class R> struct PItem {
   typename Vec<R>::T b, a, z;
   int t, q, rr, cc;
@@ -365,7 +378,12 @@ __device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, N
   const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE;
   x.b = *reinterpret_cast<const V *>(I.beta + e);
   x.a = *reinterpret_cast<const V *>(I.A + (uc[__ffs(x.m) - 1].aoff + x.rr * rowstride + x.cc * I.KS + x.q * VE));
-  x.z = P.sh_nz[x.t] ? *reinterpret_cast<const V *>(I.z + e) : Vec<R>::zero();
+  bool nz = true;
+  if (P.nzb) {
+    const int lt = (x.rr - P.a1) * P.ext2 + (x.cc - P.a2);
+    nz = (P.nzb[lt >> 5] >> (lt & 31)) & 1u;
+  }
+  x.z = nz ? *reinterpret_cast<const V *>(I.z + e) : Vec<R>::zero();
 }
 
 template <class R, int NT>
@@ -421,11 +439,6 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
     for (int cc0 = C1; cc0 < C2; cc0 += cw) {
       const int ccw = min(cw, C2 - cc0);
       const int npos = (rr1 - rr0) * ccw;
-      for (int t = tid; t < npos; t += NT) {
-        const int tr = t / ccw;
-        P.sh_nz[t] = (uint16_t)meta_nzc(I.meta[(long long)(rr0 + tr) * W + cc0 + (t - tr * ccw)]);
-      }
-      __syncthreads();
       const int nit = npos * G;
 #pragma unroll 1
       for (int i0 = tid; i0 < nit; i0 += 2 * NT) {
@@ -452,7 +465,7 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
             bk = pk[g];
           }
         score_st(I.score + pos, best);
-        I.meta[pos] = meta_pack(bk, P.sh_nz[t]);
+        reinterpret_cast<uint16_t *>(I.meta + pos)[0] = (uint16_t)bk;  // the atom half of meta
       }
       __syncthreads();
     }
@@ -497,7 +510,7 @@ template <class R, int NT> struct RoundSmem {
   static constexpr int LBUF = PatchBuf<R>::N;
   R ps[LBUF];
   uint16_t pk[LBUF];
-  uint16_t nz[LBUF];
+  uint32_t nzb[kNzWords];
   R inv_n[1024];
   R rs[NT / 64];
   int ri[NT / 64];
@@ -550,9 +563,21 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   PatchCtx<R, NT> P;
   P.sh_ps = sm.ps;
   P.sh_pk = sm.pk;
-  P.sh_nz = sm.nz;
   P.sh_inv_n = sh_inv_n;
   P.G = I.KS / VE;
+  P.a1 = a1;
+  P.a2 = a2;
+  P.ext2 = ext2;
+  P.nzb = npw <= 32 * kNzWords ? sm.nzb : nullptr;
+  if (P.nzb)
+    for (int wd = tid; wd < (npw + 31) / 32; wd += NT) {
+      uint32_t m = 0;
+      for (int b = 0; b < 32; ++b) {
+        const int t = wd * 32 + b;
+        if (t < npw && meta_nzc(I.meta[(a1 + t / ext2) * W + a2 + t % ext2])) m |= 1u << b;
+      }
+      sm.nzb[wd] = m;
+    }
 
   __syncthreads();
   for (int k = tid; k < I.KS; k += NT) sh_inv_n[k] = k < K ? I.inv_n[k] : R(0);
@@ -689,7 +714,9 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
         const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
         I.z[i0] = zn;
         const uint32_t mt = I.meta[vp];
-        I.meta[vp] = meta_pack(meta_argk(mt), meta_nzc(mt) + (zn != R(0)) - (zc != R(0)));
+        const int nzc = meta_nzc(mt) + (zn != R(0)) - (zc != R(0));
+        I.meta[vp] = meta_pack(meta_argk(mt), nzc);
+        if (P.nzb) nzb_put(P.nzb, (h0 - a1) * ext2 + (w0 - a2), nzc != 0);
         UCand<R> &u = sm.ui;
         u.k0 = k0;
         u.ch = h0;
@@ -782,7 +809,9 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
           // z and its non-zero count change now; beta and the cache in phase B
           I.z[i0] = zn;
           const uint32_t mt = I.meta[bp];
-          I.meta[bp] = meta_pack(meta_argk(mt), meta_nzc(mt) + (zn != R(0)) - (zc != R(0)));
+          const int nzc = meta_nzc(mt) + (zn != R(0)) - (zc != R(0));
+          I.meta[bp] = meta_pack(meta_argk(mt), nzc);
+          if (P.nzb) nzb_put(P.nzb, (h0 - a1) * ext2 + (w0 - a2), nzc != 0);
           dbits = delta_bits<R>(zn - zc);
           tag = cand_tag(r, k0, (unsigned)bp);
           ++my_upd;
