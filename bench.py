@@ -599,6 +599,13 @@ def main():
             k: last[f"t_worker_{k}_s"] / max(1, last["n_rounds"]) * 1e6
             for k in ("wait", "select", "collect", "apply")},
     }
+    if args.workload == "image_1024" and not args.grid and not args.tile:
+        # the same solve on a 16 x 16 grid of workers (four 32 x 32 sub-domains
+        # each), outside the timed region, beside the library's default grid
+        _, i16 = dl.dicodile_csc(X, D, lam, tol, z_out=z, **dict(opts, grid=(16, 16)))
+        out["grid_16x16"] = {"status": i16["status"], "time_to_kkt_tol_ms": i16["t_total_s"] * 1e3,
+                             "rounds": i16["n_rounds"], "updates": i16["n_updates"], "kkt": i16["kkt"],
+                             "tile": list(i16["tile"])}
     if args.workload == "image_rgb_4096":
         L = D.shape[2:]
         dl.dicodile_dict_stats(z, X, tuple(L))  # warm-up

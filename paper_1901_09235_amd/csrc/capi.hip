@@ -503,15 +503,14 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   hipLaunchKernelGGL(norms64<R>, dim3(g.K), dim3(256), 0, stream, g.K, g.P * g.L1 * g.L2, D, nrm64);
   const unsigned pb = blocks_for(HW, 256);
   if (o->warm_start) {
-    hipLaunchKernelGGL((to_position_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, z_out, zpm);
+    launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z_out, zpm);
     if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
   } else {
     HIPCK(hipMemsetAsync(zpm, 0, sizeof(R) * nz, stream));
     if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta))) return rc;
   }
   const R lam = (R)o->lambda, tol = (R)o->tol;
-  hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam, tol,
-                     o->positive, o->certify, score, meta);
+  launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
   HIPCK(hipGetLastError());
   HIPCK(hipEventRecord(ev1, stream));
   HIPCK(hipEventSynchronize(ev1));
@@ -621,8 +620,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       // (A coarser contraction here would re-inject errors above tol at every
       // chunk, and the sweep certificate could never be reached.)
       if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
-      hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam,
-                         tol, o->positive, o->certify, score, meta);
+      launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
       HIPCK(hipStreamSynchronize(stream));
       t_check += now_s() - tc0;
       continue;
@@ -644,12 +642,11 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     }
     // another pass: beta from its definition (FP64 drift correction)
     if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, false))) return rc;
-    hipLaunchKernelGGL(init_moves<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, beta, zpm, inv_n, lam,
-                       tol, o->positive, o->certify, score, meta);
+    launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
     HIPCK(hipStreamSynchronize(stream));
     t_check += now_s() - tc0;
   }
-  hipLaunchKernelGGL((to_atom_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, zpm, z_out);
+  launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
   (void)hipEventDestroy(ev0);
@@ -696,8 +693,7 @@ int corr_impl(DeviceState *ds, hipStream_t stream, Geom g, const R *X, const R *
   WS("corr_pm", sizeof(R) * HW * g.KS, gpm);
   int rc = beta_init<R>(ds, stream, g, X, D, prec, gpm);
   if (rc) return rc;
-  hipLaunchKernelGGL((to_atom_major<R, R>), dim3(blocks_for(HW, 256)), dim3(256), 0, stream, (int)HW, g.K, g.KS, gpm,
-                     out);
+  launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, gpm, out);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
   return DCDL_OK;
@@ -856,15 +852,13 @@ int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void
   if (dtype == DCDL_F32) {
     float *zpm;
     WS("zpm_check", sizeof(float) * nz, zpm);
-    hipLaunchKernelGGL((to_position_major<float, float>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS,
-                       (const float *)z, zpm);
+    launch_to_position_major<float, float>(stream, HW, g.K, g.KS, (const float *)z, zpm);
     return check64<float>(ds, stream, g, (const float *)X, (const float *)D, zpm, lambda, positive, objective, kkt,
                           nullptr);
   } else if (dtype == DCDL_F64) {
     double *zpm;
     WS("zpm_check", sizeof(double) * nz, zpm);
-    hipLaunchKernelGGL((to_position_major<double, double>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS,
-                       (const double *)z, zpm);
+    launch_to_position_major<double, double>(stream, HW, g.K, g.KS, (const double *)z, zpm);
     return check64<double>(ds, stream, g, (const double *)X, (const double *)D, zpm, lambda, positive, objective,
                            kkt, nullptr);
   }
@@ -946,7 +940,7 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
     HIPCK(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, stream));
     hipLaunchKernelGGL(list_per_atom<R>, dim3(gx, g.K), dim3(256), 0, stream, (int)HW, g.K, z, cnt + g.K, list);
     const unsigned pb = blocks_for(HW, 256);
-    hipLaunchKernelGGL((to_position_major<R, R>), dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, z, zpm);
+    launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z, zpm);
     hipLaunchKernelGGL(count_per_position<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, zpm, nzc);
     hipLaunchKernelGGL(psi_kernel<R>, dim3((unsigned)chunks.size()), dim3(256), 0, stream, g, d_chunks, list, X,
                        psi64);

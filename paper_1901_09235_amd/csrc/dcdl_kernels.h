@@ -181,47 +181,127 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
 }
 
 // ------------------------------------------------------- best-move cache
-// score[pos] = max_k score of the move at (k, pos); meta[pos] = (its atom,
-// number of non-zero atoms), from beta and z (atom stride KS).
+// Best move of every position (the cache the round kernel keeps): score and
+// atom of the largest move score over the K atoms (lowest atom on ties), and
+// the position's count of non-zero coordinates.  A position's 16-byte atom
+// groups are read by a segment of S lanes (S the power of two covering them,
+// at most a wave), so a wave reads contiguous memory, and the segment reduces
+// with shuffles.
 template <class R>
 __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R *__restrict__ beta,
                                                   const R *__restrict__ z, const R *__restrict__ inv_n, R lambda,
                                                   R tol, int positive, int certify, R *__restrict__ score,
                                                   uint32_t *__restrict__ meta) {
-  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= HW) return;
-  R best = R(-1);
-  int bk = 0, nz = 0;
-  for (int k = 0; k < K; ++k) {
-    const R zk = z[(long long)pos * KS + k];
-    nz += zk != R(0);
-    const R zn = st_target(beta[(long long)pos * KS + k], lambda, inv_n[k], positive);
-    const R sc = move_score(zk, zn, tol, certify);
-    if (sc > best) {
-      best = sc;
-      bk = k;
+  typedef typename Vec<R>::T V;
+  constexpr int VE = Vec<R>::N;
+  const int G = KS / VE;
+  int S = 1;
+  while (S < G && S < 64) S <<= 1;
+  const int lane = threadIdx.x & 63, seg = lane / S, sl = lane - seg * S;
+  const long long per_wave = 64 / S;
+  const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
+  for (long long p0 = wave * per_wave; p0 < HW; p0 += nwave * per_wave) {
+    const long long pos = p0 + seg;
+    R best = R(-1);
+    int bk = 0x7fffffff, nz = 0;
+    if (pos < HW)
+      for (int q = sl; q < G; q += S) {
+        const V b = *reinterpret_cast<const V *>(beta + pos * KS + q * VE);
+        const V zv = *reinterpret_cast<const V *>(z + pos * KS + q * VE);
+#pragma unroll
+        for (int e = 0; e < VE; ++e) {
+          const int k = q * VE + e;
+          if (k >= K) break;
+          const R zk = Vec<R>::get(zv, e);
+          nz += zk != R(0);
+          const R sc = move_score(zk, st_target(Vec<R>::get(b, e), lambda, inv_n[k], positive), tol, certify);
+          if (sc > best || (sc == best && k < bk)) {
+            best = sc;
+            bk = k;
+          }
+        }
+      }
+    for (int off = S >> 1; off > 0; off >>= 1) {
+      const R ob = __shfl_xor(best, off, 64);
+      const int ok = __shfl_xor(bk, off, 64);
+      nz += __shfl_xor(nz, off, 64);
+      if (ob > best || (ob == best && ok < bk)) {
+        best = ob;
+        bk = ok;
+      }
+    }
+    if (sl == 0 && pos < HW) {
+      score[pos] = best;
+      meta[pos] = (uint32_t)bk | ((uint32_t)nz << 16);
     }
   }
-  score[pos] = best;
-  meta[pos] = (uint32_t)bk | ((uint32_t)nz << 16);
+}
+
+template <class R>
+inline void launch_init_moves(hipStream_t st, long long HW, int K, int KS, const R *beta, const R *z, const R *inv_n,
+                              R lambda, R tol, int positive, int certify, R *score, uint32_t *meta) {
+  int G = KS / Vec<R>::N, S = 1;
+  while (S < G && S < 64) S <<= 1;
+  const long long waves = (HW + 64 / S - 1) / (64 / S);
+  const long long blocks = (waves + 3) / 4;
+  hipLaunchKernelGGL(init_moves<R>, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, (int)HW, K,
+                     KS, beta, z, inv_n, lambda, tol, positive, certify, score, meta);
 }
 
 // ---------------------------------------------------------------- layouts
-// user (K, H*W) <-> position-major (H*W, KS) with zero padding, and a type change.
+// user (K, H*W) <-> position-major (H*W, KS) with zero padding, and a type
+// change: LDS-tiled transposes of 64 positions x 64 atoms, both sides of the
+// copy coalesced.
 template <class Rs, class Rd>
 __global__ __launch_bounds__(256) void to_position_major(int HW, int K, int KS, const Rs *__restrict__ src,
                                                          Rd *__restrict__ dst) {
-  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= HW) return;
-  for (int k = 0; k < KS; ++k) dst[(long long)pos * KS + k] = k < K ? (Rd)src[(long long)k * HW + pos] : Rd(0);
+  __shared__ Rd tile[64][65];
+  const long long p0 = (long long)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  const int pn = (int)min(64ll, HW - p0), kn = min(64, KS - k0);
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int kk = i >> 6, pp = i & 63;
+    if (kk < kn && pp < pn) {
+      const int k = k0 + kk;
+      tile[kk][pp] = k < K ? (Rd)src[(long long)k * HW + p0 + pp] : Rd(0);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < pn * kn; i += 256) {
+    const int pp = i / kn, kk = i - pp * kn;
+    dst[(p0 + pp) * KS + k0 + kk] = tile[kk][pp];
+  }
 }
 
 template <class Rs, class Rd>
 __global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, const Rs *__restrict__ src,
                                                      Rd *__restrict__ dst) {
-  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= HW) return;
-  for (int k = 0; k < K; ++k) dst[(long long)k * HW + pos] = (Rd)src[(long long)pos * KS + k];
+  __shared__ Rd tile[64][65];
+  const long long p0 = (long long)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  const int pn = (int)min(64ll, HW - p0), kn = min(64, K - k0);
+  for (int i = threadIdx.x; i < pn * kn; i += 256) {
+    const int pp = i / kn, kk = i - pp * kn;
+    tile[kk][pp] = (Rd)src[(p0 + pp) * KS + k0 + kk];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int kk = i >> 6, pp = i & 63;
+    if (kk < kn && pp < pn) dst[(long long)(k0 + kk) * HW + p0 + pp] = tile[kk][pp];
+  }
+}
+
+template <class Rs, class Rd>
+inline void launch_to_position_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst) {
+  hipLaunchKernelGGL((to_position_major<Rs, Rd>), dim3((unsigned)((HW + 63) / 64), (unsigned)((KS + 63) / 64)),
+                     dim3(256), 0, st, (int)HW, K, KS, src, dst);
+}
+
+template <class Rs, class Rd>
+inline void launch_to_atom_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst) {
+  hipLaunchKernelGGL((to_atom_major<Rs, Rd>), dim3((unsigned)((HW + 63) / 64), (unsigned)((K + 63) / 64)),
+                     dim3(256), 0, st, (int)HW, K, KS, src, dst);
 }
 
 template <class Rs, class Rd>
