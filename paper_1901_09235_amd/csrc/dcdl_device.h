@@ -312,9 +312,14 @@ template <class R> struct PatchBuf {
 // coordinate (workers of up to 32 * kNzWords positions keep one).
 constexpr int kNzWords = 1024;
 
+// Rows and columns of one patch block whose cover masks (the updates whose
+// patch covers that row or column) are tabulated in LDS.
+constexpr int kMaskRows = 128, kMaskCols = 512;
+
 template <class R, int NT> struct PatchCtx {
   R *sh_ps;
   uint16_t *sh_pk;
+  uint32_t *rowm, *colm;  // cover masks of a block's rows and columns
   const R *sh_inv_n;
   uint32_t *nzb;    // bit (h - a1) * ext2 + (w - a2) set when position (h, w) of S_w has a non-zero;
                     // null for larger workers, whose patches read z everywhere
@@ -353,27 +358,37 @@ template <class R> struct UCand {
 // non-zero coordinate, z.  Their per-group best moves meet in LDS, and a last
 // pass reduces them per position into the score cache and the atom half of
 // meta.
+// n / d for 0 <= n < 8192 and 1 <= d <= 8192, with m = rcp_of(d): a
+// multiply-high by floor((2^32 - 1) / d) + 1, exact in that range (checked
+// over all of it); d = 1, whose reciprocal does not fit 32 bits, is passed through.
+__device__ __forceinline__ unsigned rcp_of(int d) { return d > 1 ? 0xffffffffu / (unsigned)d + 1u : 0u; }
+__device__ __forceinline__ int div_rcp(int n, int d, unsigned m) { return d > 1 ? (int)__umulhi((unsigned)n, m) : n; }
+
 template <class R> struct PItem {
   typename Vec<R>::T b, a, z;
-  int t, q, rr, cc;
+  int q, rr, cc;
   unsigned m;  // updates covering the item's position, the first one's DtD row in a
 };
 
+// Item `it` of a block of rows [rr0, ...) x columns [cc0, cc0 + ng / G): its
+// row, column and atom group from two multiply-high divisions (div_rcp with
+// the block's reciprocals mng of ng and mg of G), its cover mask from the
+// block's row and column tables, then its memory reads.
 template <class R, int NT>
-__device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int nc,
-                                           int it, int nit, int rr0, int cc0, int ccw, int rowstride, PItem<R> &x) {
+__device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int it,
+                                           int nit, int rr0, int cc0, int ng, unsigned mng, unsigned mg,
+                                           int rowstride, PItem<R> &x) {
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
   x.m = 0;
   if (it >= nit) return;
-  const int G = P.G;
-  x.t = it / G;
-  x.q = it - x.t * G;
-  const int tr = x.t / ccw;
+  const int tr = div_rcp(it, ng, mng);
+  const int rem = it - tr * ng;
+  const int pl = div_rcp(rem, P.G, mg);
+  x.q = rem - pl * P.G;
   x.rr = rr0 + tr;
-  x.cc = cc0 + (x.t - tr * ccw);
-  for (int c = 0; c < nc; ++c)
-    if (x.rr >= uc[c].r1 && x.rr < uc[c].r2 && x.cc >= uc[c].c1 && x.cc < uc[c].c2) x.m |= 1u << c;
+  x.cc = cc0 + pl;
+  x.m = P.rowm[tr] & P.colm[pl];
   if (!x.m) return;
   const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE;
   x.b = *reinterpret_cast<const V *>(I.beta + e);
@@ -432,19 +447,33 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
   const int W = I.W, G = P.G;
   const int rowstride = I.U2 * I.KS;
   const int ncol = C2 - C1;
-  const int cw = min(ncol, LBUF / G);
-  const int rc = max(1, LBUF / (cw * G));
+  const int cw = min(min(ncol, LBUF / G), kMaskCols);
+  const int rc = max(1, min(kMaskRows, LBUF / (cw * G)));
   for (int rr0 = R1; rr0 < R2; rr0 += rc) {
     const int rr1 = min(rr0 + rc, R2);
     for (int cc0 = C1; cc0 < C2; cc0 += cw) {
       const int ccw = min(cw, C2 - cc0);
-      const int npos = (rr1 - rr0) * ccw;
-      const int nit = npos * G;
+      const int nrow = rr1 - rr0, npos = nrow * ccw;
+      for (int j = tid; j < nrow + ccw; j += NT) {
+        unsigned mk = 0;
+        if (j < nrow) {
+          for (int c = 0; c < nc; ++c)
+            if (rr0 + j >= uc[c].r1 && rr0 + j < uc[c].r2) mk |= 1u << c;
+          P.rowm[j] = mk;
+        } else {
+          for (int c = 0; c < nc; ++c)
+            if (cc0 + j - nrow >= uc[c].c1 && cc0 + j - nrow < uc[c].c2) mk |= 1u << c;
+          P.colm[j - nrow] = mk;
+        }
+      }
+      __syncthreads();
+      const int ng = ccw * G, nit = npos * G;
+      const unsigned mng = rcp_of(ng), mg = rcp_of(G);
 #pragma unroll 1
       for (int i0 = tid; i0 < nit; i0 += 2 * NT) {
         PItem<R> x0, x1;
-        pitem_load<R, NT>(I, P, uc, nc, i0, nit, rr0, cc0, ccw, rowstride, x0);
-        pitem_load<R, NT>(I, P, uc, nc, i0 + NT, nit, rr0, cc0, ccw, rowstride, x1);
+        pitem_load<R, NT>(I, P, uc, i0, nit, rr0, cc0, ng, mng, mg, rowstride, x0);
+        pitem_load<R, NT>(I, P, uc, i0 + NT, nit, rr0, cc0, ng, mng, mg, rowstride, x1);
         if (i0 < nit && !x0.m) P.sh_ps[i0] = R(-2);  // no update covers this position: its cache stays
         if (i0 + NT < nit && !x1.m) P.sh_ps[i0 + NT] = R(-2);
         pitem_apply<R, NT>(I, P, uc, i0, rowstride, x0);
@@ -511,6 +540,7 @@ template <class R, int NT> struct RoundSmem {
   R ps[LBUF];
   uint16_t pk[LBUF];
   uint32_t nzb[kNzWords];
+  uint32_t rowm[kMaskRows], colm[kMaskCols];
   R inv_n[1024];
   R rs[NT / 64];
   int ri[NT / 64];
@@ -564,6 +594,8 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   P.sh_ps = sm.ps;
   P.sh_pk = sm.pk;
   P.sh_inv_n = sh_inv_n;
+  P.rowm = sm.rowm;
+  P.colm = sm.colm;
   P.G = I.KS / VE;
   P.a1 = a1;
   P.a2 = a2;
