@@ -703,13 +703,31 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       const int bw = e2 - s2, np = (e1 - s1) * bw;
       R vs = R(-1);
       int vp = 0x7fffffff;
-      for (int t = tid; t < np; t += NT) {
-        const int hh = s1 + t / bw, ww = s2 + t % bw;
-        const int pos = hh * W + ww;
-        const R sc = score_ld(I.score + pos);
-        if (sc > vs || (sc == vs && pos < vp)) {
-          vs = sc;
-          vp = pos;
+      {
+        // four positions per pass with their loads in flight together; the
+        // (row, column) of position t steps by NT each time
+        const int dh = NT / bw, dw = NT - dh * bw;
+        int th = tid / bw, tw = tid - th * bw;
+        for (int t = tid; t < np; t += 4 * NT) {
+          R sc[4];
+          int ps[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            ps[u] = (s1 + th) * W + s2 + tw;
+            sc[u] = t + u * NT < np ? score_ld(I.score + ps[u]) : R(-1);
+            tw += dw;
+            th += dh;
+            if (tw >= bw) {
+              tw -= bw;
+              ++th;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            if (sc[u] > vs || (sc[u] == vs && ps[u] < vp)) {
+              vs = sc[u];
+              vp = ps[u];
+            }
         }
       }
       block_argmax<R, NT>(vs, vp, sh_rs, sh_ri);
@@ -811,15 +829,36 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       const int vw = u2 - v2, nv = (u1 - v1) * vw;
       my_chk += nv;
       int lk = 0;
-      for (int t = tid; t < nv; t += NT) {
-        const int hh = v1 + t / vw, ww = v2 + t % vw;
-        if (hh >= a1 && hh < b1 && ww >= a2 && ww < b2) continue;
-        const R sc = score_ld(I.score + hh * W + ww);
-        if (sc > bs) {
-          lk = 1;
-        } else if (sc == bs) {
-          const int owner = part_owner(hh, H, I.W1) * I.W2 + part_owner(ww, W, I.W2);
-          if (owner < w) lk = 1;
+      {
+        const int dh = NT / vw, dw = NT - dh * vw;
+        int th = tid / vw, tw = tid - th * vw;
+        for (int t = tid; t < nv; t += 4 * NT) {
+          R sc[4];
+          int hq[4], wq[4];
+          bool use[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            hq[u] = v1 + th;
+            wq[u] = v2 + tw;
+            use[u] = t + u * NT < nv && !(hq[u] >= a1 && hq[u] < b1 && wq[u] >= a2 && wq[u] < b2);
+            sc[u] = use[u] ? score_ld(I.score + hq[u] * W + wq[u]) : R(-1);
+            tw += dw;
+            th += dh;
+            if (tw >= vw) {
+              tw -= vw;
+              ++th;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            if (!use[u]) continue;
+            if (sc[u] > bs) {
+              lk = 1;
+            } else if (sc[u] == bs) {
+              const int owner = part_owner(hq[u], H, I.W1) * I.W2 + part_owner(wq[u], W, I.W2);
+              if (owner < w) lk = 1;
+            }
+          }
         }
       }
       locked = block_or<NT>(lk, sh_ri);
