@@ -364,19 +364,24 @@ template <class R> struct UCand {
 __device__ __forceinline__ unsigned rcp_of(int d) { return d > 1 ? 0xffffffffu / (unsigned)d + 1u : 0u; }
 __device__ __forceinline__ int div_rcp(int n, int d, unsigned m) { return d > 1 ? (int)__umulhi((unsigned)n, m) : n; }
 
+// A patch item is a position and a pair of its 16-byte atom groups (2 q2 and,
+// if it exists, 2 q2 + 1): the row, column, cover and address work of an item
+// serves eight FP32 (four FP64) atoms, and its six vector reads are in flight
+// together.
 template <class R> struct PItem {
-  typename Vec<R>::T b, a, z;
-  int q, rr, cc;
-  unsigned m;  // updates covering the item's position, the first one's DtD row in a
+  typename Vec<R>::T b0, b1, a0, a1, z0, z1;
+  int q2, rr, cc;
+  unsigned m;  // updates covering the item's position, the first one's DtD row in a0/a1
+  bool two;    // the second group exists (an odd group count leaves the last pair half)
 };
 
-// Item `it` of a block of rows [rr0, ...) x columns [cc0, cc0 + ng / G): its
-// row, column and atom group from two multiply-high divisions (div_rcp with
-// the block's reciprocals mng of ng and mg of G), its cover mask from the
+// Item `it` of a block of rows [rr0, ...) x columns [cc0, cc0 + ng / G2): its
+// row, column and group pair from two multiply-high divisions (div_rcp with
+// the block's reciprocals mng of ng and mg of G2), its cover mask from the
 // block's row and column tables, then its memory reads.
 template <class R, int NT>
 __device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, NT> &P, const UCand<R> *uc, int it,
-                                           int nit, int rr0, int cc0, int ng, unsigned mng, unsigned mg,
+                                           int nit, int rr0, int cc0, int ng, int G2, unsigned mng, unsigned mg,
                                            int rowstride, PItem<R> &x) {
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
@@ -384,21 +389,26 @@ __device__ __forceinline__ void pitem_load(const Inst<R> &I, const PatchCtx<R, N
   if (it >= nit) return;
   const int tr = div_rcp(it, ng, mng);
   const int rem = it - tr * ng;
-  const int pl = div_rcp(rem, P.G, mg);
-  x.q = rem - pl * P.G;
+  const int pl = div_rcp(rem, G2, mg);
+  x.q2 = rem - pl * G2;
   x.rr = rr0 + tr;
   x.cc = cc0 + pl;
   x.m = P.rowm[tr] & P.colm[pl];
   if (!x.m) return;
-  const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE;
-  x.b = *reinterpret_cast<const V *>(I.beta + e);
-  x.a = *reinterpret_cast<const V *>(I.A + (uc[__ffs(x.m) - 1].aoff + x.rr * rowstride + x.cc * I.KS + x.q * VE));
+  x.two = 2 * x.q2 + 1 < P.G;
+  const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + 2 * x.q2 * VE;
+  const long long ea = uc[__ffs(x.m) - 1].aoff + x.rr * rowstride + x.cc * I.KS + 2 * x.q2 * VE;
+  x.b0 = *reinterpret_cast<const V *>(I.beta + e);
+  x.b1 = x.two ? *reinterpret_cast<const V *>(I.beta + e + VE) : Vec<R>::zero();
+  x.a0 = *reinterpret_cast<const V *>(I.A + ea);
+  x.a1 = x.two ? *reinterpret_cast<const V *>(I.A + ea + VE) : Vec<R>::zero();
   bool nz = true;
   if (P.nzb) {
     const int lt = (x.rr - P.a1) * P.ext2 + (x.cc - P.a2);
     nz = (P.nzb[lt >> 5] >> (lt & 31)) & 1u;
   }
-  x.z = nz ? *reinterpret_cast<const V *>(I.z + e) : Vec<R>::zero();
+  x.z0 = nz ? *reinterpret_cast<const V *>(I.z + e) : Vec<R>::zero();
+  x.z1 = nz && x.two ? *reinterpret_cast<const V *>(I.z + e + VE) : Vec<R>::zero();
 }
 
 template <class R, int NT>
@@ -407,29 +417,42 @@ __device__ __forceinline__ void pitem_apply(const Inst<R> &I, const PatchCtx<R, 
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
   if (!x.m) return;
-  V b = x.b;
+  V b0 = x.b0, b1 = x.b1;
   unsigned m = x.m;
   bool first = true;
   while (m) {
     const int c = __ffs(m) - 1;
     m &= m - 1;
     const UCand<R> &u = uc[c];
-    const V av = first ? x.a
-                       : *reinterpret_cast<const V *>(I.A + (u.aoff + x.rr * rowstride + x.cc * I.KS + x.q * VE));
+    V av0 = x.a0, av1 = x.a1;
+    if (!first) {
+      const long long ea = u.aoff + x.rr * rowstride + x.cc * I.KS + 2 * x.q2 * VE;
+      av0 = *reinterpret_cast<const V *>(I.A + ea);
+      av1 = x.two ? *reinterpret_cast<const V *>(I.A + ea + VE) : Vec<R>::zero();
+    }
     first = false;
-    const V bold = b;
-    b = Vec<R>::fma_neg(b, av, u.delta);
-    if (x.rr == u.ch && x.cc == u.cw0 && x.q == u.k0 / VE)
-      Vec<R>::set(b, u.k0 % VE, Vec<R>::get(bold, u.k0 % VE));  // the updated coordinate itself
+    const V bold0 = b0, bold1 = b1;
+    b0 = Vec<R>::fma_neg(b0, av0, u.delta);
+    b1 = Vec<R>::fma_neg(b1, av1, u.delta);
+    if (x.rr == u.ch && x.cc == u.cw0) {  // the updated coordinate itself keeps its value
+      const int kq = u.k0 / VE, ke = u.k0 % VE;
+      if (kq == 2 * x.q2) Vec<R>::set(b0, ke, Vec<R>::get(bold0, ke));
+      if (kq == 2 * x.q2 + 1) Vec<R>::set(b1, ke, Vec<R>::get(bold1, ke));
+    }
   }
-  *reinterpret_cast<V *>(I.beta + ((long long)x.rr * I.W + x.cc) * I.KS + x.q * VE) = b;
+  const long long e = ((long long)x.rr * I.W + x.cc) * I.KS + 2 * x.q2 * VE;
+  *reinterpret_cast<V *>(I.beta + e) = b0;
+  if (x.two) *reinterpret_cast<V *>(I.beta + e + VE) = b1;
   R best = R(-1);
   int bk = 0;
+  const int k0 = 2 * x.q2 * VE;
 #pragma unroll
-  for (int e = 0; e < VE; ++e) {
-    const int k = x.q * VE + e;
-    const R zn = st_target(Vec<R>::get(b, e), I.lambda, P.sh_inv_n[k], I.positive);
-    const R sc = k < I.K ? move_score(Vec<R>::get(x.z, e), zn, I.tol, I.certify) : R(-1);
+  for (int e2 = 0; e2 < 2 * VE; ++e2) {
+    const int k = k0 + e2;
+    const R bv = e2 < VE ? Vec<R>::get(b0, e2) : Vec<R>::get(b1, e2 - VE);
+    const R zv = e2 < VE ? Vec<R>::get(x.z0, e2) : Vec<R>::get(x.z1, e2 - VE);
+    const R zn = st_target(bv, I.lambda, P.sh_inv_n[k < 1024 ? k : 0], I.positive);
+    const R sc = k < I.K ? move_score(zv, zn, I.tol, I.certify) : R(-1);
     if (sc > best) {
       best = sc;
       bk = k;
@@ -444,11 +467,11 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
                                             int R1, int R2, int C1, int C2) {
   constexpr int LBUF = PatchBuf<R>::N;
   const int tid = threadIdx.x;
-  const int W = I.W, G = P.G;
+  const int W = I.W, G2 = (P.G + 1) / 2;
   const int rowstride = I.U2 * I.KS;
   const int ncol = C2 - C1;
-  const int cw = min(min(ncol, LBUF / G), kMaskCols);
-  const int rc = max(1, min(kMaskRows, LBUF / (cw * G)));
+  const int cw = min(min(ncol, LBUF / G2), kMaskCols);
+  const int rc = max(1, min(kMaskRows, LBUF / (cw * G2)));
   for (int rr0 = R1; rr0 < R2; rr0 += rc) {
     const int rr1 = min(rr0 + rc, R2);
     for (int cc0 = C1; cc0 < C2; cc0 += cw) {
@@ -467,28 +490,25 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
         }
       }
       __syncthreads();
-      const int ng = ccw * G, nit = npos * G;
-      const unsigned mng = rcp_of(ng), mg = rcp_of(G);
+      const int ng = ccw * G2, nit = npos * G2;
+      const unsigned mng = rcp_of(ng), mg = rcp_of(G2);
 #pragma unroll 1
-      for (int i0 = tid; i0 < nit; i0 += 2 * NT) {
-        PItem<R> x0, x1;
-        pitem_load<R, NT>(I, P, uc, i0, nit, rr0, cc0, ng, mng, mg, rowstride, x0);
-        pitem_load<R, NT>(I, P, uc, i0 + NT, nit, rr0, cc0, ng, mng, mg, rowstride, x1);
-        if (i0 < nit && !x0.m) P.sh_ps[i0] = R(-2);  // no update covers this position: its cache stays
-        if (i0 + NT < nit && !x1.m) P.sh_ps[i0 + NT] = R(-2);
-        pitem_apply<R, NT>(I, P, uc, i0, rowstride, x0);
-        pitem_apply<R, NT>(I, P, uc, i0 + NT, rowstride, x1);
+      for (int it = tid; it < nit; it += NT) {
+        PItem<R> x;
+        pitem_load<R, NT>(I, P, uc, it, nit, rr0, cc0, ng, G2, mng, mg, rowstride, x);
+        if (!x.m) P.sh_ps[it] = R(-2);  // no update covers this position: its cache stays
+        pitem_apply<R, NT>(I, P, uc, it, rowstride, x);
       }
       __syncthreads();
       for (int t = tid; t < npos; t += NT) {
-        const R *pp = P.sh_ps + t * G;
+        const R *pp = P.sh_ps + t * G2;
         if (pp[0] == R(-2)) continue;
         const int tr = t / ccw;
         const int pos = (rr0 + tr) * W + cc0 + (t - tr * ccw);
-        const uint16_t *pk = P.sh_pk + t * G;
+        const uint16_t *pk = P.sh_pk + t * G2;
         R best = pp[0];
         int bk = pk[0];
-        for (int g = 1; g < G; ++g)
+        for (int g = 1; g < G2; ++g)
           if (pp[g] > best) {
             best = pp[g];
             bk = pk[g];
