@@ -301,9 +301,9 @@ __device__ __forceinline__ int block_or(int v, int *sh) {
 
 // ------------------------------------------------------------- the round kernel
 
-// Items (position, atom group) one LDS block of a patch holds: 24 KB of
-// staging for FP32 and 20 KB for FP64, so that four FP32 or three FP64
-// workers share a CU.
+// Items (position, atom-group pair) one LDS block of a patch holds: 24 KB of
+// best-move staging for FP32 and 20 KB for FP64, so that four FP32 or three
+// FP64 workers share a CU.
 template <class R> struct PatchBuf {
   static constexpr int N = sizeof(R) == 4 ? 4096 : 2048;
 };
@@ -352,12 +352,14 @@ template <class R> struct UCand {
 // the updates in increasing worker order, as applying them one after another
 // would.  Every thread of the workgroup takes part.
 //
-// The box is cut into blocks of at most LBUF (position, atom group) items,
-// run two per thread and pass with every load of both in flight before either
-// is used: beta, the DtD row and, where the worker's LDS bitmask marks a
-// non-zero coordinate, z.  Their per-group best moves meet in LDS, and a last
-// pass reduces them per position into the score cache and the atom half of
-// meta.
+// The box is cut into blocks of at most LBUF items (a position and a pair of
+// its atom groups), each block with LDS tables of the updates covering its
+// rows and its columns.  A thread runs one item per pass with all its reads
+// in flight before any is used: beta, the DtD row and, where the worker's LDS
+// bitmask marks a non-zero coordinate, z.  The items' best moves meet in LDS,
+// and a last pass reduces them per position into the score cache and the
+// atom half of meta.
+
 // n / d for 0 <= n < 8192 and 1 <= d <= 8192, with m = rcp_of(d): a
 // multiply-high by floor((2^32 - 1) / d) + 1, exact in that range (checked
 // over all of it); d = 1, whose reciprocal does not fit 32 bits, is passed through.
