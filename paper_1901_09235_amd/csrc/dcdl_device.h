@@ -448,12 +448,14 @@ __device__ __forceinline__ void pitem_apply(const Inst<R> &I, const PatchCtx<R, 
   R best = R(-1);
   int bk = 0;
   const int k0 = 2 * x.q2 * VE;
+  const V in0 = *reinterpret_cast<const V *>(P.sh_inv_n + k0);
+  const V in1 = x.two ? *reinterpret_cast<const V *>(P.sh_inv_n + k0 + VE) : Vec<R>::zero();
 #pragma unroll
   for (int e2 = 0; e2 < 2 * VE; ++e2) {
     const int k = k0 + e2;
     const R bv = e2 < VE ? Vec<R>::get(b0, e2) : Vec<R>::get(b1, e2 - VE);
     const R zv = e2 < VE ? Vec<R>::get(x.z0, e2) : Vec<R>::get(x.z1, e2 - VE);
-    const R zn = st_target(bv, I.lambda, P.sh_inv_n[k < 1024 ? k : 0], I.positive);
+    const R zn = st_target(bv, I.lambda, e2 < VE ? Vec<R>::get(in0, e2) : Vec<R>::get(in1, e2 - VE), I.positive);
     const R sc = k < I.K ? move_score(zv, zn, I.tol, I.certify) : R(-1);
     if (sc > best) {
       best = sc;
@@ -493,7 +495,7 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
       }
       __syncthreads();
       const int ng = ccw * G2, nit = npos * G2;
-      const unsigned mng = rcp_of(ng), mg = rcp_of(G2);
+      const unsigned mng = rcp_of(ng), mg = rcp_of(G2), rcw = rcp_of(ccw);
 #pragma unroll 1
       for (int it = tid; it < nit; it += NT) {
         PItem<R> x;
@@ -505,7 +507,7 @@ __device__ __forceinline__ void patch_union(const Inst<R> &I, const PatchCtx<R, 
       for (int t = tid; t < npos; t += NT) {
         const R *pp = P.sh_ps + t * G2;
         if (pp[0] == R(-2)) continue;
-        const int tr = t / ccw;
+        const int tr = div_rcp(t, ccw, rcw);
         const int pos = (rr0 + tr) * W + cc0 + (t - tr * ccw);
         const uint16_t *pk = P.sh_pk + t * G2;
         R best = pp[0];
