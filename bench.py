@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--ablation-cap", type=float, default=30.0,
                     help="ablation: wall-clock cap of one solve in seconds")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-grid16", action="store_true",
+                    help="image_1024: skip the extra solve on a 16 x 16 worker grid (profiling runs)")
     ap.add_argument("--cpu-sample", type=int, default=128, help="side of the oracle's crop")
     ap.add_argument("--probe-mib", type=int, default=1024, help="copy-probe size (0: skip)")
     return ap.parse_args()
@@ -599,7 +601,7 @@ def main():
             k: last[f"t_worker_{k}_s"] / max(1, last["n_rounds"]) * 1e6
             for k in ("wait", "select", "collect", "apply")},
     }
-    if args.workload == "image_1024" and not args.grid and not args.tile:
+    if args.workload == "image_1024" and not args.grid and not args.tile and not args.no_grid16:
         # the same solve on a 16 x 16 grid of workers (four 32 x 32 sub-domains
         # each), outside the timed region, beside the library's default grid
         _, i16 = dl.dicodile_csc(X, D, lam, tol, z_out=z, **dict(opts, grid=(16, 16)))
