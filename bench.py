@@ -36,15 +36,18 @@ def kernel_source_digest() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def stored_traffic(workload: str):
+def stored_traffic(workload: str, grid, tile):
     """HBM bytes per launch of the round kernel from the committed rocprofv3
-    FETCH_SIZE/WRITE_SIZE runs, if they were taken on the current sources."""
+    FETCH_SIZE/WRITE_SIZE runs, if they were taken on the current sources and
+    on the same worker grid and sub-domain tile."""
     path = os.path.join(PROFILES, f"traffic_lgcd_rounds_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
     if rec.get("kernel_source_digest") != kernel_source_digest():
+        return None
+    if rec.get("grid") != list(grid) or rec.get("tile") != list(tile):
         return None
     return rec
 
@@ -617,7 +620,7 @@ def main():
         torch.cuda.synchronize()
         out["dict_stats_ms"] = (time.perf_counter() - t0) * 1e3
         out["dict_stats_shapes"] = {"ztz": list(ztz.shape), "ztX": list(ztX.shape)}
-    tr = stored_traffic(pb.name)
+    tr = stored_traffic(pb.name, out["config"]["grid"], out["config"]["tile"])
     if tr is not None:
         out["roofline"]["traffic"] = tr["bytes_per_launch"]
         out["roofline"]["traffic_source"] = tr["source"]

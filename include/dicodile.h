@@ -112,7 +112,9 @@ typedef struct {
                              Sec. 5 only; pair it with div_guard) */
   int32_t threads;        /* threads per worker workgroup: 64, 128, 192, 256, 512 or 1024; 0 -> 256 */
   int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
-  int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library */
+  int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library: ceil(extent / tile)
+                             workers per axis, each at least L long, scaled down to the
+                             workgroups that fit on the device together */
   int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
   int32_t refresh_every;  /* rebuild beta from its FP64 definition every this many sweeps of rounds
                              (periodic drift correction); 0 -> only after a failed final check */
