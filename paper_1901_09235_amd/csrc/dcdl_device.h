@@ -704,8 +704,12 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
         const int pos = hh * W + ww;
         if (tid == 0) {
           const long long i0 = (long long)pos * I.KS + k;
-          sh_rs[0] = move_score(I.z[i0], st_target(I.beta[i0], I.lambda, sh_inv_n[k], I.positive), I.tol,
-                                I.certify);
+          const R zc = I.z[i0];
+          const R zn = st_target(I.beta[i0], I.lambda, sh_inv_n[k], I.positive);
+          sm.ck0 = k;
+          sm.czc = zc;
+          sm.czn = zn;
+          sh_rs[0] = move_score(zc, zn, I.tol, I.certify);
         }
         __syncthreads();
         const R sc = sh_rs[0];
@@ -754,6 +758,13 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
             }
         }
       }
+      // with one visit per round each thread whose own best could be the
+      // candidate (a position of the sub-domain scoring >= tol) fetches its
+      // meta word while the block reduces, so the winning thread reads the
+      // candidate's z and beta one dependent load earlier
+      const int lp = vp;
+      const bool lok = inner == 1 && vs >= I.tol && vs > R(0);
+      const uint32_t lmeta = lok ? I.meta[lp] : 0u;
       block_argmax<R, NT>(vs, vp, sh_rs, sh_ri);
       if (!(vs >= I.tol && vs > R(0))) {
         ++quiet;
@@ -772,6 +783,13 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
           bp = vp;
           hh0 = h0;
           hw0 = w0;
+          if (lok && lp == vp) {
+            const int k0 = meta_argk(lmeta);
+            const long long i0 = (long long)vp * I.KS + k0;
+            sm.ck0 = k0;
+            sm.czc = I.z[i0];
+            sm.czn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
+          }
         } else if (restart < 0) {
           restart = visit;  // a second band-reaching candidate waits for the next round
         }
@@ -820,12 +838,12 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     }
     // The visits above read only S_w, which this worker alone writes and
     // finished patching in its last phase B; so do the candidate's reads
-    // below.  Only the soft-lock test (the neighbours' scores of round r - 1)
+    // (in the visit with one visit per round, below with several).  Only the soft-lock test (the neighbours' scores of round r - 1)
     // and the reuse of the candidate slot (read by the neighbours in round
     // r - 1) need the neighbours' progress.
     if (tid == 0) {
-      if (has) {
-        const int k0 = rnd ? bk : meta_argk(I.meta[bp]);
+      if (has && inner != 1) {
+        const int k0 = meta_argk(I.meta[bp]);
         const long long i0 = (long long)bp * I.KS + k0;
         sm.ck0 = k0;
         sm.czc = I.z[i0];

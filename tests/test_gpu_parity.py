@@ -80,7 +80,7 @@ def test_objective_and_kkt_match_oracle(lib, dtype):
 # ------------------------------------------------------------------- solver
 
 def _solve_and_compare(lib, pb, dtype, grid=None, tile=None, positive=False, threads=0,
-                       obj_tol=1e-6, kkt_tol=1e-4, tol_rel=None):
+                       obj_tol=1e-6, kkt_tol=1e-4, tol_rel=None, **opts):
     lam = pb.lambda_frac * oracle.lambda_max(pb.X, pb.D, positive)
     if dtype == torch.float64:
         tol = 1e-10 * lam if tol_rel is None else tol_rel * lam
@@ -91,7 +91,7 @@ def _solve_and_compare(lib, pb, dtype, grid=None, tile=None, positive=False, thr
         D = pb.D.astype(np.float32).astype(np.float64)
     z, info = lib.dicodile_csc(dev(X, dtype), dev(D, dtype), lam, tol, positive=positive,
                                grid=grid, tile=tile, threads=threads, max_rounds=2_000_000,
-                               timeout_s=60)
+                               timeout_s=60, **opts)
     assert info["status"] == "OK", info
     Zg = host(z)
     Zo, oinfo = oracle.lgcd(X, D, lam, 1e-10 * lam, positive=positive)
@@ -125,6 +125,17 @@ def test_csc_small_image_fp64_grid_and_ragged_tiles(lib):
     pb = _small_image(8, size=(77, 61), K=3, L=(6, 5))
     _, info = _solve_and_compare(lib, pb, torch.float64, grid=(3, 4), tile=(7, 9))
     assert info["n_softlocked"] >= 0 and info["grid"] == (3, 4)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+@pytest.mark.parametrize("inner", [2, 4])
+def test_csc_several_visits_per_round(lib, dtype, inner):
+    """Several sub-domain visits per worker and round: interior candidates
+    are applied inside the visit loop, a band-reaching one waits for the
+    round's exchange; the minimiser is the oracle's."""
+    pb = _small_image(8, size=(77, 61), K=3, L=(6, 5))
+    _, info = _solve_and_compare(lib, pb, dtype, grid=(2, 2), tile=(7, 6), inner=inner)
+    assert info["grid"] == (2, 2) and info["n_updates"] > 0
 
 
 def test_csc_multichannel_positive(lib):
