@@ -948,11 +948,18 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       unsigned long long t = 0;
       int ok = 1;
       const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+      const int rtag = r & ((1 << kRoundBits) - 1);
       for (;;) {
+        // the tag and the progress word are read together, one round trip
+        // per poll
         t = ld_shared_u64(I.cand + 2 * n);
-        if (tag_round(t) == (r & ((1 << kRoundBits) - 1))) break;
-        if (ld_shared_i32(I.prog + n) == 0x7fffffff) {  // neighbour has left
-          t = cand_tag(r, 0, kNoPos);
+        const int pg = ld_shared_i32(I.prog + n);
+        if (tag_round(t) == rtag) break;
+        if (pg == 0x7fffffff) {
+          // the neighbour has left; it stored its last tag before its
+          // progress word, so a tag of this round is seen by a reread
+          t = ld_shared_u64(I.cand + 2 * n);
+          if (tag_round(t) != rtag) t = cand_tag(r, 0, kNoPos);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
