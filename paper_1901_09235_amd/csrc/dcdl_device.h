@@ -572,6 +572,7 @@ template <class R, int NT> struct RoundSmem {
   int wok[9];  // per-neighbour result of the progress wait
   int ck0;       // the held candidate's atom, current value and target
   R czc, czn;
+  uint32_t cmeta;  // ... and its position's meta word (LGCD rules)
   UCand<R> ui;  // an interior candidate applied within phase A
   unsigned long long tag[9];
   R delta[9];
@@ -787,6 +788,7 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
             const int k0 = meta_argk(lmeta);
             const long long i0 = (long long)vp * I.KS + k0;
             sm.ck0 = k0;
+            sm.cmeta = lmeta;
             sm.czc = I.z[i0];
             sm.czn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
           }
@@ -843,9 +845,11 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
     // r - 1) need the neighbours' progress.
     if (tid == 0) {
       if (has && inner != 1) {
-        const int k0 = meta_argk(I.meta[bp]);
+        const uint32_t mt = I.meta[bp];
+        const int k0 = meta_argk(mt);
         const long long i0 = (long long)bp * I.KS + k0;
         sm.ck0 = k0;
+        sm.cmeta = mt;
         sm.czc = I.z[i0];
         sm.czn = st_target(I.beta[i0], I.lambda, sh_inv_n[k0], I.positive);
       }
@@ -921,7 +925,8 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
           const R zn = sm.czn;
           // z and its non-zero count change now; beta and the cache in phase B
           I.z[i0] = zn;
-          const uint32_t mt = I.meta[bp];
+          // the meta word read with the candidate: nothing writes it since
+          const uint32_t mt = rnd ? I.meta[bp] : sm.cmeta;
           const int nzc = meta_nzc(mt) + (zn != R(0)) - (zc != R(0));
           I.meta[bp] = meta_pack(meta_argk(mt), nzc);
           if (P.nzb) nzb_put(P.nzb, (h0 - a1) * ext2 + (w0 - a2), nzc != 0);
