@@ -574,8 +574,6 @@ template <class R, int NT> struct RoundSmem {
   R czc, czn;
   uint32_t cmeta;  // ... and its position's meta word (LGCD rules)
   UCand<R> ui;  // an interior candidate applied within phase A
-  unsigned long long tag[9];
-  R delta[9];
   int nbr[9];
   UCand<R> uc[9];
   int nuc, ub[4];  // updates touching S_w and the bounding box of their patches
@@ -592,8 +590,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
   int *const sh_ri = sm.ri;
   int &sh_exit = sm.exit_f;
   int &sh_cok = sm.cok;
-  unsigned long long *const sh_tag = sm.tag;
-  R *const sh_delta = sm.delta;
   int *const sh_nbr = sm.nbr;
   const int tid = threadIdx.x;
   const int nW = I.W1 * I.W2;
@@ -947,7 +943,11 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
       tk_mark = t;
     }
 
-    // ---- collect this round's candidates of the 3x3 neighbourhood
+    // ---- collect this round's candidates of the 3x3 neighbourhood; lane q
+    // also clips neighbour q's update to S_w for phase B
+    bool uval = false;
+    int uk0 = 0, uch = 0, ucw = 0, ur1 = 0, ur2 = 0, uc1 = 0, uc2 = 0;
+    R udl = R(0);
     if (tid < nn) {
       const int n = sh_nbr[tid];
       unsigned long long t = 0;
@@ -974,9 +974,61 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
           break;
         }
       }
-      sh_tag[tid] = t;
-      sh_delta[tid] = tag_pos(t) != kNoPos ? bits_delta<R>(ld_shared_u64(I.cand + 2 * n + 1)) : R(0);
+      const unsigned cpos = tag_pos(t);
+      if (cpos != kNoPos) {
+        udl = bits_delta<R>(ld_shared_u64(I.cand + 2 * n + 1));
+        uk0 = tag_k0(t);
+        uch = (int)(cpos / (unsigned)W);
+        ucw = (int)(cpos - (unsigned)uch * (unsigned)W);
+        ur1 = max(uch - I.L1 + 1, a1);
+        ur2 = min(uch + I.L1, b1);
+        uc1 = max(ucw - I.L2 + 1, a2);
+        uc2 = min(ucw + I.L2, b2);
+        uval = ur1 < ur2 && uc1 < uc2;
+      }
       if (!ok) sh_cok = 0;
+    }
+    if (tid < 64) {
+      // the touching updates in neighbour order, their bounding box and the
+      // patched area, over the first wave's lanes
+      const unsigned long long bal = __ballot(uval);
+      if (uval) {
+        UCand<R> &u = sm.uc[__popcll(bal & ((1ull << tid) - 1ull))];
+        u.k0 = uk0;
+        u.ch = uch;
+        u.cw0 = ucw;
+        u.r1 = ur1;
+        u.r2 = ur2;
+        u.c1 = uc1;
+        u.c2 = uc2;
+        u.aoff = ((uk0 * I.U1 - uch + I.L1 - 1) * I.U2 - ucw + I.L2 - 1) * I.KS;
+        u.delta = udl;
+      }
+      int x1 = uval ? ur1 : b1, x2 = uval ? ur2 : a1, y1 = uval ? uc1 : b2, y2 = uval ? uc2 : a2;
+      unsigned pa = uval ? (unsigned)((ur2 - ur1) * (uc2 - uc1)) : 0u;
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        x1 = min(x1, __shfl_xor(x1, off, 16));
+        x2 = max(x2, __shfl_xor(x2, off, 16));
+        y1 = min(y1, __shfl_xor(y1, off, 16));
+        y2 = max(y2, __shfl_xor(y2, off, 16));
+        pa += __shfl_xor(pa, off, 16);
+      }
+      if (tid == 0) {
+        const int nu = __popcll(bal);
+        sm.nuc = nu;
+        sm.ub[0] = x1;
+        sm.ub[1] = x2;
+        sm.ub[2] = y1;
+        sm.ub[3] = y2;
+        my_patch += pa;
+        // One pass over the bounding box pays for small patches, whose cost is
+        // mostly per-update latency (positions no update covers cost no loads).
+        // Large patches (over 1024 positions) are bandwidth-bound and go one by
+        // one: measured on 32x32 atoms (3969-position patches) the single pass
+        // costs 15-20% of the rounds' time.
+        sm.ub_union = nu > 1 && (long long)I.U1 * I.U2 <= 1024;
+      }
     }
     __syncthreads();
     if (!sh_cok) {
@@ -991,45 +1043,6 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
 
     // ---- phase B: apply the accepted candidates that touch S_w (eq. beta_update),
     // all in one pass over the bounding box of their patches
-    if (tid == 0) {
-      int nu = 0, u1 = b1, u2 = a1, v1 = b2, v2 = a2;
-      for (int q = 0; q < nn; ++q) {
-        const unsigned long long tg = sh_tag[q];
-        const unsigned cpos = tag_pos(tg);
-        if (cpos == kNoPos) continue;
-        const int ch = (int)(cpos / (unsigned)W), cw0 = (int)(cpos - (unsigned)ch * (unsigned)W);
-        const int r1 = max(ch - I.L1 + 1, a1), r2 = min(ch + I.L1, b1);
-        const int c1 = max(cw0 - I.L2 + 1, a2), c2 = min(cw0 + I.L2, b2);
-        if (r1 >= r2 || c1 >= c2) continue;
-        UCand<R> &u = sm.uc[nu++];
-        u.k0 = tag_k0(tg);
-        u.ch = ch;
-        u.cw0 = cw0;
-        u.r1 = r1;
-        u.r2 = r2;
-        u.c1 = c1;
-        u.c2 = c2;
-        u.aoff = ((u.k0 * I.U1 - ch + I.L1 - 1) * I.U2 - cw0 + I.L2 - 1) * I.KS;
-        u.delta = sh_delta[q];
-        u1 = min(u1, r1);
-        u2 = max(u2, r2);
-        v1 = min(v1, c1);
-        v2 = max(v2, c2);
-        my_patch += (unsigned long long)(r2 - r1) * (c2 - c1);
-      }
-      sm.nuc = nu;
-      sm.ub[0] = u1;
-      sm.ub[1] = u2;
-      sm.ub[2] = v1;
-      sm.ub[3] = v2;
-      // One pass over the bounding box pays for small patches, whose cost is
-      // mostly per-update latency (positions no update covers cost no loads).
-      // Large patches (over 1024 positions) are bandwidth-bound and go one by
-      // one: measured on 32x32 atoms (3969-position patches) the single pass
-      // costs 15-20% of the rounds' time.
-      sm.ub_union = nu > 1 && (long long)I.U1 * I.U2 <= 1024;
-    }
-    __syncthreads();
     if (sm.nuc > 0) {
       quiet = 0;
       if (sm.ub_union || sm.nuc == 1) {
