@@ -89,7 +89,10 @@ typedef enum {
 
 /* Problem shape.  ndim = 1: T[0] = T, L[0] = L (T[1], L[1] ignored).
  * ndim = 2: T = (T1, T2), L = (L1, L2).  Requires 1 <= L_i <= T_i, P >= 1,
- * 1 <= K <= 1024. */
+ * 1 <= K <= 1024, T1 T2 < 2^31, and (the round kernel's 32-bit offsets into
+ * the update table of eq. beta_update) K (2 L1 - 1)(2 L2 - 1) K4 +
+ * (T1 + 2 L1 - 1)(2 L2 - 1) K4 + (T2 + 2 L2 - 1) K4 < 2^31 with K4 = K
+ * rounded up to a multiple of 4; DCDL_EINVAL otherwise. */
 typedef struct {
   int32_t ndim;
   int32_t P;
@@ -173,7 +176,13 @@ const char *dicodile_version(void);
 /* Message of the last error on the calling thread ("" if none). */
 const char *dicodile_last_error(void);
 
-/* Release the per-device workspace and cached tables of the current device. */
+/* Release the library's own device resources on every device it has used:
+ * each device is synchronised, its workspace buffers are freed and the
+ * library-owned stream is destroyed; the caller's current device is kept.
+ * Servers are not touched (dicodile_server_destroy).  Call it before the HIP
+ * runtime is torn down (the Python binding does so at interpreter exit); the
+ * next call re-creates what it needs.  DCDL_EHIP if a HIP call fails (the
+ * remaining resources are still released). */
 int dicodile_release(void);
 
 /* DtD (Sec. 3, the kernel of eq. beta_update):

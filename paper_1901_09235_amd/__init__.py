@@ -684,6 +684,23 @@ class Server:
         self.close()
 
 
+def _release_at_exit():
+    """Hands the library's device workspaces and its stream back before the
+    interpreter exits, while the HIP runtime is still whole (the runtime's own
+    teardown runs later, from C-level exit handlers).  Nothing is done when the
+    library was never loaded or no device was ever initialised."""
+    if _lib is None:
+        return
+    import sys
+    torch = sys.modules.get("torch")
+    if torch is None or not torch.cuda.is_initialized():
+        return
+    torch.cuda.synchronize()
+    _lib.dicodile_release()
+
+
 import atexit as _atexit  # noqa: E402
 
+# atexit runs handlers last-registered first: servers close, then the release
+_atexit.register(_release_at_exit)
 _atexit.register(_close_live_servers)

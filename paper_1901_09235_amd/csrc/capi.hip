@@ -142,6 +142,15 @@ int make_geom(const dcdl_shape *s, Geom *g) {
   if (L1 < 1 || L2 < 1 || T1 < L1 || T2 < L2) return fail(DCDL_EINVAL, "need 1 <= L_i <= T_i");
   if (T1 * T2 > (1ll << 31) - 1 || (T1 - L1 + 1) * (T2 - L2 + 1) * (long long)s->K > (1ll << 40))
     return fail(DCDL_EINVAL, "problem too large for 32-bit position indices");
+  {
+    // the round kernel addresses the apply table A[k0][d1][d2][k] and a
+    // patch's rows (row * (2 L2 - 1) * KS) with 32-bit offsets; KS is at most
+    // K rounded up to four
+    const long long ks = (s->K + 3) / 4 * 4, u1 = 2ll * L1 - 1, u2 = 2ll * L2 - 1;
+    if ((long long)s->K * u1 * u2 * ks + (T1 + u1) * u2 * ks + (T2 + u2) * ks >= (1ll << 31))
+      return fail(DCDL_EINVAL, "K * (2 L1 - 1) * (2 L2 - 1) * K = %lld apply-table entries exceed 32-bit offsets",
+                  (long long)s->K * u1 * u2 * ks);
+  }
   g->P = s->P;
   g->K = s->K;
   g->L1 = L1;
@@ -753,20 +762,37 @@ const char *dicodile_version(void) { return "dicodile-mi355x 0.1 (gfx950)"; }
 
 const char *dicodile_last_error(void) { return g_err.c_str(); }
 
+// Frees every workspace buffer and destroys the library-owned stream of every
+// device the library has touched, each with that device current; the caller's
+// current device is restored.  Servers own their resources and are released
+// by dicodile_server_destroy.
 int dicodile_release(void) {
   g_err.clear();
-  DeviceState *ds = device_state(nullptr);
-  if (!ds) return fail(DCDL_EHIP, "hipGetDevice failed");
-  Guard guard_(ds);
-  HIPCK(hipDeviceSynchronize());
-  for (auto &kv : ds->bufs)
-    if (kv.second.p) HIPCK(hipFree(kv.second.p));
-  ds->bufs.clear();
-  if (ds->aux) {
-    HIPCK(hipStreamDestroy(ds->aux));
-    ds->aux = nullptr;
+  int cur = 0;
+  HIPCK(hipGetDevice(&cur));
+  std::vector<std::pair<int, DeviceState *>> devs;
+  {
+    std::lock_guard<std::mutex> lk(g_devices_mu);
+    for (auto &kv : g_devices) devs.push_back(kv);
   }
-  return DCDL_OK;
+  int rc = DCDL_OK;
+  for (auto &kv : devs) {
+    DeviceState *ds = kv.second;
+    Guard guard_(ds);
+    if (hipSetDevice(kv.first) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
+      rc = fail(DCDL_EHIP, "device %d: synchronisation before release failed", kv.first);
+      continue;
+    }
+    for (auto &b : ds->bufs)
+      if (b.second.p && hipFree(b.second.p) != hipSuccess) rc = fail(DCDL_EHIP, "hipFree failed");
+    ds->bufs.clear();
+    if (ds->aux) {
+      if (hipStreamDestroy(ds->aux) != hipSuccess) rc = fail(DCDL_EHIP, "hipStreamDestroy failed");
+      ds->aux = nullptr;
+    }
+  }
+  HIPCK(hipSetDevice(cur));
+  return rc;
 }
 
 int dicodile_dtd(const dcdl_shape *shape, dcdl_dtype dtype, const void *D, void *dtd_out, void *stream_) {

@@ -108,6 +108,20 @@ def test_argument_checks_before_device_access(lib):
     assert rc == -1 and b"selection rule" in lib.dicodile_last_error()
     with pytest.raises(dl.DicodileError):
         dl.make_opts(1.0, 0.0, 0, strategy="sideways")
+    # an apply table of K (2L1-1)(2L2-1) K entries beyond 32-bit offsets is
+    # refused by the shape check, before any launch (K = 1024 atoms of 32x32)
+    big = dl.Shape()
+    big.ndim, big.P, big.K = 2, 1, 1024
+    big.T[0], big.T[1], big.L[0], big.L[1] = 256, 256, 32, 32
+    o = dl.make_opts(1.0, 0.0, 0)
+    rc = lib.dicodile_csc(ctypes.byref(big), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(o),
+                          ctypes.c_void_p(1), ctypes.byref(info), None)
+    assert rc == -1 and b"32-bit offsets" in lib.dicodile_last_error()
+    assert lib.dicodile_dtd(ctypes.byref(big), 0, ctypes.c_void_p(1), ctypes.c_void_p(1), None) == -1
+    big.K = 256  # 256 * 63 * 63 * 256 = 2.6e8 entries: accepted by the shape check
+    rc = lib.dicodile_csc(ctypes.byref(big), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(dl.make_opts(-1.0, 0.0, 0)),
+                          ctypes.c_void_p(1), ctypes.byref(info), None)
+    assert rc == -1 and b"lambda" in lib.dicodile_last_error()
     # server calls: NULL handles and arguments are rejected before any device access
     assert lib.dicodile_server_create(None, 0, None, None, None) == -1
     assert lib.dicodile_server_submit(None, None, None, None, None, None) == -1
