@@ -120,7 +120,8 @@ typedef struct {
                              workgroups that fit on the device together */
   int32_t warm_start;     /* 1: z_out holds the initial iterate on entry */
   int32_t refresh_every;  /* rebuild beta from its FP64 definition every this many sweeps of rounds
-                             (periodic drift correction); 0 -> only after a failed final check */
+                             (periodic drift correction); 0 -> only after a failed final check.
+                             A failed check rebuilds beta from the same FP64 contraction */
   int32_t max_polish;     /* extra solve passes after a failed final check; 0 -> 2 */
   int32_t inner;          /* sub-domain visits per worker per round; 0 -> 1 */
   int32_t beta_prec;      /* dcdl_corr_prec of the contraction that initialises beta from X
@@ -134,7 +135,9 @@ typedef struct {
   int32_t strategy;       /* dcdl_select; 0 -> LGCD.  GREEDY and CYCLIC override tile, RANDOM
                              ignores tile and inner.  Only dicodile_csc (and dicodile_cdl's CSC
                              steps) accept a rule other than LGCD */
-  int32_t reserved;
+  int32_t refresh_limit;  /* at most this many periodic drift corrections (0 -> no limit); with
+                             refresh_every = S and refresh_limit = 1 the solve corrects beta once,
+                             after S sweeps, and then runs to the certificate */
   uint64_t seed;          /* seed of the RANDOM rule's generator */
 } dcdl_csc_opts;
 
@@ -168,6 +171,12 @@ typedef struct {
   double beta_drift;         /* at the first FP64 check: max |beta kept by the rounds - (corr(X - Z*D, D)
                                 + n z) in FP64|, / lambda: the error of the incremental beta against
                                 its FP64 definition (NaN if no check ran) */
+  double t_init_corr_s;      /* HIP-event time of the contraction that initialised beta (0 after a
+                                warm start, whose beta comes from an FP64 contraction counted below) */
+  double t_corr64_s;         /* HIP-event time of the FP64 contractions: every check, drift correction
+                                and warm start, summed */
+  int32_t n_corr64;          /* number of those FP64 contractions */
+  int32_t init_prec;         /* dcdl_corr_prec the initialisation ran at (AUTO and fallbacks resolved) */
 } dcdl_csc_info;
 
 /* Library version string (static storage). */

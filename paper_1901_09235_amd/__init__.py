@@ -53,7 +53,7 @@ class CscOpts(ctypes.Structure):
                 ("inner", ctypes.c_int32), ("beta_prec", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
                 ("kkt_target", ctypes.c_double), ("strategy", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("refresh_limit", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class CscInfo(ctypes.Structure):
@@ -69,7 +69,9 @@ class CscInfo(ctypes.Structure):
                 ("n_visits", ctypes.c_int64), ("n_checked", ctypes.c_int64),
                 ("n_patched", ctypes.c_int64), ("t_worker_wait_s", ctypes.c_double),
                 ("t_worker_select_s", ctypes.c_double), ("t_worker_collect_s", ctypes.c_double),
-                ("t_worker_apply_s", ctypes.c_double), ("beta_drift", ctypes.c_double)]
+                ("t_worker_apply_s", ctypes.c_double), ("beta_drift", ctypes.c_double),
+                ("t_init_corr_s", ctypes.c_double), ("t_corr64_s", ctypes.c_double),
+                ("n_corr64", ctypes.c_int32), ("init_prec", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -259,7 +261,7 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
               div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0,
-              beta_prec=0, strategy=0, seed=0) -> CscOpts:
+              beta_prec=0, strategy=0, seed=0, refresh_limit=0) -> CscOpts:
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -271,6 +273,7 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
         g = (grid, 0) if isinstance(grid, int) else tuple(grid)
         o.grid[0], o.grid[1] = int(g[0]), int(g[1])
     o.warm_start, o.refresh_every, o.max_polish = int(warm_start), int(refresh_every), int(max_polish)
+    o.refresh_limit = int(refresh_limit)
     o.max_rounds, o.div_guard, o.timeout_s = int(max_rounds), float(div_guard), float(timeout_s)
     o.kkt_target = float(kkt_target)
     o.inner = int(inner)
@@ -295,9 +298,9 @@ def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
     """Solve eq. csc on the device.  Returns (z, info dict).
 
     Keyword options mirror dcdl_csc_opts: positive, certify, grid, tile,
-    threads, warm_start, refresh_every, max_polish, max_rounds, div_guard,
-    timeout_s, kkt_target, no_soft_lock, inner, beta_prec, strategy ("lgcd",
-    "greedy", "cyclic", "random" or the dcdl_select code) and seed.  A
+    threads, warm_start, refresh_every, refresh_limit, max_polish, max_rounds,
+    div_guard, timeout_s, kkt_target, no_soft_lock, inner, beta_prec, strategy
+    ("lgcd", "greedy", "cyclic", "random" or the dcdl_select code) and seed.  A
     NOT_CONVERGED status is reported in info['status']; errors raise
     DicodileError."""
     torch = _torch()

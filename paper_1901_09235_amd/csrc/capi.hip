@@ -171,6 +171,35 @@ inline unsigned grid_stride_blocks(long long n) {
   return (unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
+// HIP events bracketing launches on one stream; the elapsed times are summed
+// when the end event has completed.
+struct CorrTimer {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  double s = 0.0;
+  int n = 0;
+  int begin(hipStream_t st) {
+    if (!e[0]) {
+      HIPCK(hipEventCreate(&e[0]));
+      HIPCK(hipEventCreate(&e[1]));
+    }
+    HIPCK(hipEventRecord(e[0], st));
+    return DCDL_OK;
+  }
+  int end(hipStream_t st) {
+    HIPCK(hipEventRecord(e[1], st));
+    HIPCK(hipEventSynchronize(e[1]));
+    float ms = 0.f;
+    HIPCK(hipEventElapsedTime(&ms, e[0], e[1]));
+    s += ms * 1e-3;
+    ++n;
+    return DCDL_OK;
+  }
+  ~CorrTimer() {
+    if (e[0]) (void)hipEventDestroy(e[0]);
+    if (e[1]) (void)hipEventDestroy(e[1]);
+  }
+};
+
 // ------------------------------------------------------------- kernels
 template <class R>
 int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *dtd, R *A, R *inv_n) {
@@ -228,11 +257,15 @@ int corr_beta_at(hipStream_t stream, const Geom &g, int prec, const R *Xin, cons
   return fail(DCDL_EINVAL, "the BF16 contractions need FP32 data");
 }
 
-// beta = corr(X, D) (Z = 0) at precision `prec` (a dcdl_corr_prec).
+// beta = corr(X, D) (Z = 0) at precision `prec` (a dcdl_corr_prec); the
+// contraction alone is timed by `tm` when given, and the resolved precision is
+// stored in `used`.
 template <class R>
-int beta_init(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, int want, R *beta) {
+int beta_init(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, int want, R *beta,
+              CorrTimer *tm = nullptr, int *used = nullptr) {
   const int prec = resolve_prec(want, std::is_same<R, float>::value, g);
   if (prec < 0) return fail(DCDL_EINVAL, "beta_prec %d is not available for this dtype", want);
+  if (used) *used = prec;
   CorrOut ob{};
   ob.beta = beta;
   void *pk = nullptr;
@@ -243,7 +276,13 @@ int beta_init(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, co
     int rc = mf_pack<R>(stream, g, pl, mp, D, pk);
     if (rc) return rc;
   }
-  return corr_beta_at<R>(stream, g, prec, X, D, pk, ob);
+  if (tm) {
+    int rc = tm->begin(stream);
+    if (rc) return rc;
+  }
+  int rc = corr_beta_at<R>(stream, g, prec, X, D, pk, ob);
+  if (rc || !tm) return rc;
+  return tm->end(stream);
 }
 
 // D packed for the FP64 matrix-core contraction in the "dpk64" slot, or NULL
@@ -286,10 +325,14 @@ int residual64_async(hipStream_t stream, const Geom &g, const R *X, const double
 
 // FP64 objective and strict KKT of a position-major z.  Leaves the FP64
 // residual in the "res64" slot and D in FP64 in the "D64" slot.
+// With beta_fix (which may be beta_cmp) the same contraction also rebuilds
+// beta = G + n z there in FP64 rounded to R: the check doubles as a drift
+// correction.  `tm` times the contraction.
 template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
             int positive, double *obj, double *kkt, long long *nnz, const R *beta_cmp = nullptr,
-            const double *nrm64 = nullptr, double *drift = nullptr) {
+            const double *nrm64 = nullptr, double *drift = nullptr, R *beta_fix = nullptr,
+            CorrTimer *tm = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -308,10 +351,13 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.beta_cmp = beta_cmp;
   o.nrm = nrm64;
   o.result2 = scal + 4;
+  o.beta = beta_fix;
   void *pk64;
   if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
+  if (tm && (rc = tm->begin(stream))) return rc;
   rc = corr64<R, CORR_KKT>(stream, g, res, D64, pk64, o);
   if (rc) return rc;
+  if (tm && (rc = tm->end(stream))) return rc;
   double h[5];
   HIPCK(hipMemcpyAsync(h, scal, 40, hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
@@ -327,7 +373,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
 // With fresh = false it reuses the residual and D64 left by check64.
 template <class R>
 int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
-                  const double *nrm64, R *beta, bool fresh) {
+                  const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -346,7 +392,10 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   void *pk64;
   int rc = pack64<R>(ds, stream, g, D, &pk64);
   if (rc) return rc;
-  return corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
+  if (tm && (rc = tm->begin(stream))) return rc;
+  rc = corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
+  if (rc || !tm) return rc;
+  return tm->end(stream);
 }
 
 // Exact FP64 norms from D.
@@ -514,13 +563,14 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   HIPCK(hipMemsetAsync(inv_n, 0, sizeof(R) * g.KS, stream));
   if ((rc = run_dtd<R>(ds, stream, g, D, dtd, A, inv_n))) return rc;
   hipLaunchKernelGGL(norms64<R>, dim3(g.K), dim3(256), 0, stream, g.K, g.P * g.L1 * g.L2, D, nrm64);
-  const unsigned pb = blocks_for(HW, 256);
+  CorrTimer tm_init, tm64;
+  int init_prec = DCDL_CORR_F64;
   if (o->warm_start) {
     launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z_out, zpm);
-    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
+    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64))) return rc;
   } else {
     HIPCK(hipMemsetAsync(zpm, 0, sizeof(R) * nz, stream));
-    if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta))) return rc;
+    if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta, &tm_init, &init_prec))) return rc;
   }
   const R lam = (R)o->lambda, tol = (R)o->tol;
   launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
@@ -569,6 +619,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   const double kkt_target = o->kkt_target > 0 ? o->kkt_target : 1e-4;
   const int max_polish = o->max_polish > 0 ? o->max_polish : 2;
   const int refresh = o->refresh_every > 0 ? o->refresh_every : 0;
+  const int refresh_limit = o->refresh_limit > 0 ? o->refresh_limit : 0;
+  int n_refresh = 0;
   long long rounds_left = o->max_rounds > 0 ? o->max_rounds : (1ll << 30);
   double t_cd = 0, t_check = 0, obj = 0, kkt = 0;
   long long nnz = 0;
@@ -580,7 +632,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   const long long timeout_ticks = 500000000ll;  // 5 s per neighbour wait, 100 MHz clock
   for (;;) {
     ++passes;
-    long long chunk = refresh > 0 ? (long long)refresh * pl.mmax : rounds_left;
+    const bool refresh_due = refresh > 0 && (refresh_limit == 0 || n_refresh < refresh_limit);
+    long long chunk = refresh_due ? (long long)refresh * pl.mmax : rounds_left;
     if (chunk > rounds_left) chunk = rounds_left;
     if (chunk > (1ll << 22) - 2) chunk = (1ll << 22) - 2;  // candidate tags hold 22 bits of round
     hi.max_rounds = chunk;
@@ -632,15 +685,19 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       // a refresh chunk ended: beta rebuilt from its FP64 definition, no check.
       // (A coarser contraction here would re-inject errors above tol at every
       // chunk, and the sweep certificate could never be reached.)
-      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true))) return rc;
+      ++n_refresh;
+      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64))) return rc;
       launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
       HIPCK(hipStreamSynchronize(stream));
       t_check += now_s() - tc0;
       continue;
     }
-    // FP64 check of the iterate (objective, strict KKT, drift of the maintained beta)
+    // FP64 check of the iterate (objective, strict KKT, drift of the maintained
+    // beta); the same contraction rebuilds beta from its FP64 definition for a
+    // polish pass
     double drift_now = 0;
-    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now);
+    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now,
+                    beta, &tm64);
     if (rc) return rc;
     if (n_checks++ == 0) beta_drift = drift_now;
     if (sweep_done && kkt <= kkt_target) {
@@ -653,8 +710,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       t_check += now_s() - tc0;
       break;
     }
-    // another pass: beta from its definition (FP64 drift correction)
-    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, false))) return rc;
+    // another pass: beta was rebuilt from its FP64 definition by the check
     launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
     HIPCK(hipStreamSynchronize(stream));
     t_check += now_s() - tc0;
@@ -694,6 +750,10 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     info->t_worker_collect_s = tw_col;
     info->t_worker_apply_s = tw_app;
     info->beta_drift = beta_drift;
+    info->t_init_corr_s = tm_init.s;
+    info->t_corr64_s = tm64.s;
+    info->n_corr64 = tm64.n;
+    info->init_prec = init_prec;
   }
   return status;
 }

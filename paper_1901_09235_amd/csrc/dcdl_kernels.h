@@ -94,7 +94,10 @@ __global__ __launch_bounds__(256) void dtd_kernel(Geom g, const R *__restrict__ 
 enum CorrMode { CORR_BETA = 0, CORR_KKT = 1, CORR_ABSMAX = 2 };
 
 struct CorrOut {
-  void *beta;          // CORR_BETA: (H, W, KS) in the output type, padding written as 0
+  void *beta;          // CORR_BETA: (H, W, KS) in the output type, padding written as 0.
+                       // CORR_KKT, optional: also receives beta = G + n z (needs nrm); it may
+                       // alias beta_cmp (each element is compared before the same thread
+                       // overwrites it), which makes the check a drift correction as well
   const void *zpm;     // z (H, W, KS) in the working type: + n_k z (BETA) or the KKT test
   const double *nrm;   // n_k in FP64 (CORR_BETA with zpm)
   double lambda;       // CORR_KKT
@@ -160,6 +163,7 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
           red = fmax(red, v);
           if (o.beta_cmp)
             red2 = fmax(red2, fabs(gv + o.nrm[k] * z - (double)reinterpret_cast<const Rz *>(o.beta_cmp)[pos * g.KS + k]));
+          if (o.beta) reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = (Rz)(gv + o.nrm[k] * z);
         } else {
           const double gv = (double)acc[q];
           red = fmax(red, o.positive ? gv : fabs(gv));

@@ -264,6 +264,7 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
             if (o.beta_cmp)
               red2 = fmax(red2, fabs(gv + o.nrm[k] * z -
                                      (double)reinterpret_cast<const Rz *>(o.beta_cmp)[pos * g.KS + k]));
+            if (o.beta) reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = (Rz)(gv + o.nrm[k] * z);
           } else {
             red = fmax(red, o.positive ? gv : fabs(gv));
           }

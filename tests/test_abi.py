@@ -59,6 +59,8 @@ int main(void) {
          sizeof(dcdl_cdl_info), offsetof(dcdl_cdl_opts, dict), offsetof(dcdl_cdl_info, n_updates));
   printf("%zu %zu\\n", sizeof(dcdl_tune_info), offsetof(dcdl_csc_info, beta_drift));
   printf("%zu %zu %d\\n", offsetof(dcdl_csc_opts, strategy), offsetof(dcdl_csc_opts, seed), (int)DCDL_SELECT_RANDOM);
+  printf("%zu %zu %zu %zu\\n", offsetof(dcdl_csc_opts, refresh_limit), offsetof(dcdl_csc_info, t_init_corr_s),
+         offsetof(dcdl_csc_info, n_corr64), offsetof(dcdl_csc_info, init_prec));
   return 0;
 }
 """)
@@ -83,6 +85,9 @@ int main(void) {
     assert last == [ctypes.sizeof(dl.TuneInfo), dl.CscInfo.beta_drift.offset]
     sel = [int(v) for v in lines[6].split()]
     assert sel == [dl.CscOpts.strategy.offset, dl.CscOpts.seed.offset, dl.SELECT["random"]]
+    tail = [int(v) for v in lines[7].split()]
+    assert tail == [dl.CscOpts.refresh_limit.offset, dl.CscInfo.t_init_corr_s.offset, dl.CscInfo.n_corr64.offset,
+                    dl.CscInfo.init_prec.offset]
 
 
 def test_argument_checks_before_device_access(lib):

@@ -159,3 +159,48 @@ def test_periodic_refresh_reaches_oracle(lib, beta_prec):
     fo = oracle.objective(X, Dd, Zo, lam)
     fg = oracle.objective(X, Dd, z.double().cpu().numpy(), lam)
     assert (fg - fo) / fo <= 1e-6
+
+
+def test_single_drift_correction_after_bf16_start(lib):
+    """The precision pattern of the large image: a BF16 matrix-core start,
+    one FP64 drift correction after two sweeps (refresh_limit = 1), the FP64
+    check.  The correction and every check are FP64 contractions (counted and
+    timed in info); the result meets the oracle's objective and strict KKT."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(12)), 6, 3, (8, 8))
+    pb = synth.make_problem("p", 904, P=3, T=(72, 80), K=6, L=(8, 8), rho=0.004, amp="exp", sigma=0.05, D=D)
+    X = pb.X.astype(np.float32).astype(np.float64)
+    Dd = D.astype(np.float32).astype(np.float64)
+    lam = 0.1 * oracle.lambda_max(X, Dd)
+    z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
+                               beta_prec="bf16", refresh_every=2, refresh_limit=1, grid=(3, 3), timeout_s=60)
+    assert info["status"] == "OK", info
+    assert info["init_prec"] == 2 and info["t_init_corr_s"] > 0
+    # the one correction, then one check per pass after it
+    assert info["n_corr64"] == info["n_passes"], info
+    assert info["t_corr64_s"] > 0
+    Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
+    fo = oracle.objective(X, Dd, Zo, lam)
+    Zg = z.double().cpu().numpy()
+    assert (oracle.objective(X, Dd, Zg, lam) - fo) / fo <= 1e-6
+    assert oracle.kkt(X, Dd, Zg, lam) <= 1e-4
+
+
+def test_failed_check_rebuilds_beta_in_the_same_contraction(lib):
+    """A check that fails (here: a BF16 start and no earlier correction, so
+    the first pass converges on a perturbed beta) rebuilds beta from the FP64
+    contraction it has just run: every pass costs one FP64 contraction, and
+    the polished result meets the oracle."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(13)), 5, 2, 40)
+    pb = synth.make_problem("p", 905, P=2, T=8000, K=5, L=40, rho=0.005, amp="exp", sigma=0.1, D=D)
+    X = pb.X.astype(np.float32).astype(np.float64)
+    Dd = D.astype(np.float32).astype(np.float64)
+    lam = 0.1 * oracle.lambda_max(X, Dd)
+    z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
+                               beta_prec="bf16", grid=6, max_polish=4, timeout_s=60)
+    assert info["status"] == "OK", info
+    assert info["n_corr64"] == info["n_passes"], info
+    Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
+    fo = oracle.objective(X, Dd, Zo, lam)
+    Zg = z.double().cpu().numpy()
+    assert (oracle.objective(X, Dd, Zg, lam) - fo) / fo <= 1e-6
+    assert oracle.kkt(X, Dd, Zg, lam) <= 1e-4
