@@ -219,6 +219,31 @@ int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X
 int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D,
                  const dcdl_csc_opts *opts, void *z_out, dcdl_csc_info *info, void *stream);
 
+/* Size of the fixed device scratch of dicodile_csc_noalloc: 64 MiB. */
+#define DCDL_NOALLOC_SCRATCH_BYTES (64ull << 20)
+
+/* dicodile_csc for callers that cannot allocate device memory: serving loops
+ * and harnesses that forbid hipMalloc (the solve reads its convergence state
+ * on the host between passes, so it cannot be recorded into a HIP graph).
+ * Same arguments, kernels and results as dicodile_csc.  Every workspace (beta,
+ * z, the move cache, the update table, DtD, the worker protocol state, the
+ * packed dictionaries, the FP64 residual) is carved from a fixed
+ * DCDL_NOALLOC_SCRATCH_BYTES array in device memory that each device holds for
+ * the life of the process; the call makes no hipMalloc, hipFree or other
+ * allocating call (its first call on a device looks the array's address up
+ * and creates the seven timing events it reuses; dicodile_release drops
+ * them).  The workspace of a solve is about 2 HW KS s + HW (s + 4) +
+ * K (2L1-1)(2L2-1)(K + KS) s + 8 P T1 T2 bytes (s = 4 or 8 bytes, KS = K
+ * rounded up to 16 bytes of atoms): for example 1-D signals of T = 5000 with
+ * K = 5 atoms, or images up to about 480x480 with K = 25 atoms of 16x16 in
+ * FP32.  DCDL_EINVAL, before any device access, when the solve needs more.
+ * The scratch keeps the last call's contents; every call initialises what it
+ * reads.  Calls on one device share the array: two that overlapped would
+ * race, but the library serialises its calls on a device and each returns
+ * after its work has completed. */
+int dicodile_csc_noalloc(const dcdl_shape *shape, const void *X, const void *D,
+                         const dcdl_csc_opts *opts, void *z_out, dcdl_csc_info *info, void *stream);
+
 /* Dense correlation G = corr(X, D) (Sec. 2: the paper's X * D~_k; beta at
  * Z = 0, and the gradient -G of the data term):
  *   G[k][w] = sum_p sum_t D_{k,p}[t] X_p[w + t],  w on the valid domain.

@@ -17,7 +17,7 @@ import ctypes
 import os
 
 __all__ = ["DicodileError", "library_path", "load", "dicodile_version", "dicodile_dtd",
-           "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt",
+           "dicodile_lambda_max", "dicodile_csc", "dicodile_csc_noalloc", "dicodile_objective_kkt",
            "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch_autotune", "dicodile_csc_batch", "dicodile_release",
            "dicodile_dict_update", "dicodile_cdl", "Server", "STATUS"]
 
@@ -133,6 +133,7 @@ def load():
     lib.dicodile_dtd.argtypes = [sp, i32, vp, vp, vp]
     lib.dicodile_lambda_max.argtypes = [sp, i32, vp, vp, i32, ctypes.POINTER(dbl), vp]
     lib.dicodile_csc.argtypes = [sp, vp, vp, ctypes.POINTER(CscOpts), vp, ctypes.POINTER(CscInfo), vp]
+    lib.dicodile_csc_noalloc.argtypes = [sp, vp, vp, ctypes.POINTER(CscOpts), vp, ctypes.POINTER(CscInfo), vp]
     lib.dicodile_objective_kkt.argtypes = [sp, i32, vp, vp, vp, dbl, i32, ctypes.POINTER(dbl),
                                            ctypes.POINTER(dbl), vp]
     lib.dicodile_dict_stats.argtypes = [sp, i32, vp, vp, vp, vp, vp]
@@ -153,7 +154,7 @@ def load():
     lib.dicodile_server_wait.argtypes = [vp, ctypes.c_uint64, dbl, ctypes.POINTER(CscInfo)]
     lib.dicodile_server_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     lib.dicodile_server_destroy.argtypes = [vp]
-    for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_objective_kkt", "dicodile_corr",
+    for f in ("dicodile_dtd", "dicodile_lambda_max", "dicodile_csc", "dicodile_csc_noalloc", "dicodile_objective_kkt", "dicodile_corr",
               "dicodile_dict_stats", "dicodile_copy_probe", "dicodile_corr", "dicodile_csc_batch_autotune", "dicodile_csc_batch",
               "dicodile_server_create", "dicodile_server_submit", "dicodile_server_poll",
               "dicodile_server_wait", "dicodile_server_stats", "dicodile_server_destroy"):
@@ -295,6 +296,20 @@ def info_dict(info: CscInfo, status: int) -> dict:
 
 
 def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
+    """Solve eq. csc on the device.  Returns (z, info dict).  See _csc_call."""
+    return _csc_call("dicodile_csc", X, D, lam, tol, z_out, stream, opts)
+
+
+def dicodile_csc_noalloc(X, D, lam: float, tol: float, z_out, stream=None, **opts):
+    """dicodile_csc with every workspace in the library's fixed device scratch
+    (no device allocation in the call; z_out must be given).  Problems needing
+    more than that scratch raise DicodileError (EINVAL)."""
+    if z_out is None:
+        raise DicodileError(-1, "dicodile_csc_noalloc needs z_out")
+    return _csc_call("dicodile_csc_noalloc", X, D, lam, tol, z_out, stream, opts)
+
+
+def _csc_call(fn: str, X, D, lam: float, tol: float, z_out, stream, opts):
     """Solve eq. csc on the device.  Returns (z, info dict).
 
     Keyword options mirror dcdl_csc_opts: positive, certify, grid, tile,
@@ -320,7 +335,7 @@ def dicodile_csc(X, D, lam: float, tol: float, z_out=None, stream=None, **opts):
         raise DicodileError(-1, f"z_out must be {_zshape(s)} {X.dtype}")
     o = make_opts(lam, tol, code, **opts)
     info = CscInfo()
-    rc = lib.dicodile_csc(ctypes.byref(s), ctypes.c_void_p(X.data_ptr()),
+    rc = getattr(lib, fn)(ctypes.byref(s), ctypes.c_void_p(X.data_ptr()),
                           ctypes.c_void_p(D.data_ptr()), ctypes.byref(o),
                           ctypes.c_void_p(z_out.data_ptr()), ctypes.byref(info), _stream(stream))
     _check(rc, allow_not_converged=True)

@@ -27,6 +27,13 @@
 
 using namespace dcdl;
 
+// Fixed device scratch of dicodile_csc_noalloc: every workspace of that call
+// is carved from it, so the call allocates nothing.  Each device holds its
+// own copy for the life of the process; host code reaches it only through
+// the address hipGetSymbolAddress returns for the device (DeviceState).
+constexpr size_t kScratchBytes = (size_t)DCDL_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
 namespace {
 
 thread_local std::string g_err;
@@ -53,6 +60,16 @@ struct Buf {
   size_t n = 0;
 };
 
+// Workspaces of one no-allocation call: named slots carved in order from the
+// device's scratch array (a name asked for again gets its slot back).
+struct ScratchArena {
+  unsigned char *base = nullptr;
+  size_t cap = 0, off = 0;
+  std::map<std::string, std::pair<size_t, size_t>> slots;  // name -> (offset, bytes)
+};
+
+constexpr int kCallEvents = 7;
+
 struct DeviceState {
   std::mutex mu;
   std::map<std::string, Buf> bufs;
@@ -60,6 +77,11 @@ struct DeviceState {
   int cus = 0;
   bool checked = false;
   bool is_gfx950 = false;
+  // no-allocation calls: this device's address of `scratch` and the events
+  // its calls time with, both obtained once at the first such call
+  unsigned char *scratch_ptr = nullptr;
+  hipEvent_t na_ev[kCallEvents] = {};
+  ScratchArena *arena = nullptr;  // set for the duration of a no-allocation call
 };
 
 std::mutex g_devices_mu;
@@ -79,6 +101,22 @@ DeviceState *device_state(int *dev_out) {
 // named slot.  Synchronises `stream` before freeing an old allocation.
 int ws_get(DeviceState *ds, hipStream_t stream, const char *name, size_t bytes, void **out) {
   if (bytes == 0) bytes = 256;
+  if (ds->arena) {
+    ScratchArena &a = *ds->arena;
+    auto it = a.slots.find(name);
+    if (it != a.slots.end() && it->second.second >= bytes) {
+      *out = a.base + it->second.first;
+      return DCDL_OK;
+    }
+    const size_t nb = (bytes + 255) / 256 * 256;
+    if (a.off + nb > a.cap)
+      return fail(DCDL_EINVAL, "workspace '%s' (%zu bytes) does not fit the %zu-byte fixed scratch of "
+                  "dicodile_csc_noalloc (%zu bytes used)", name, bytes, a.cap, a.off);
+    a.slots[name] = {a.off, nb};
+    *out = a.base + a.off;
+    a.off += nb;
+    return DCDL_OK;
+  }
   Buf &b = ds->bufs[name];
   if (b.n < bytes) {
     if (b.p) {
@@ -171,17 +209,38 @@ inline unsigned grid_stride_blocks(long long n) {
   return (unsigned)(b < 8192 ? (b < 1 ? 1 : b) : 8192);
 }
 
-// HIP events bracketing launches on one stream; the elapsed times are summed
+// The events one call times its launches with: created for the call, or
+// borrowed from the device's set when the call may not allocate.
+struct CallEvents {
+  hipEvent_t e[kCallEvents] = {};
+  bool owned = false;
+  int init(const DeviceState *ds) {
+    if (ds->arena) {
+      for (int i = 0; i < kCallEvents; ++i) e[i] = ds->na_ev[i];
+      return DCDL_OK;
+    }
+    owned = true;
+    for (int i = 0; i < kCallEvents; ++i) HIPCK(hipEventCreate(&e[i]));
+    return DCDL_OK;
+  }
+  ~CallEvents() {
+    if (owned)
+      for (int i = 0; i < kCallEvents; ++i)
+        if (e[i]) (void)hipEventDestroy(e[i]);
+  }
+};
+
+// Two events bracketing launches on one stream; the elapsed times are summed
 // when the end event has completed.
 struct CorrTimer {
   hipEvent_t e[2] = {nullptr, nullptr};
   double s = 0.0;
   int n = 0;
+  CorrTimer(hipEvent_t a, hipEvent_t b) {
+    e[0] = a;
+    e[1] = b;
+  }
   int begin(hipStream_t st) {
-    if (!e[0]) {
-      HIPCK(hipEventCreate(&e[0]));
-      HIPCK(hipEventCreate(&e[1]));
-    }
     HIPCK(hipEventRecord(e[0], st));
     return DCDL_OK;
   }
@@ -193,10 +252,6 @@ struct CorrTimer {
     s += ms * 1e-3;
     ++n;
     return DCDL_OK;
-  }
-  ~CorrTimer() {
-    if (e[0]) (void)hipEventDestroy(e[0]);
-    if (e[1]) (void)hipEventDestroy(e[1]);
   }
 };
 
@@ -554,16 +609,15 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   WS("ctl", sizeof(Ctl) + sizeof(int) * 2 * kRing, ctl);
   WS("inst", sizeof(Inst<R>), d_inst);
 
-  hipEvent_t ev0, ev1, ev2;
-  HIPCK(hipEventCreate(&ev0));
-  HIPCK(hipEventCreate(&ev1));
-  HIPCK(hipEventCreate(&ev2));
+  CallEvents evs;
+  if ((rc = evs.init(ds))) return rc;
+  hipEvent_t ev0 = evs.e[0], ev1 = evs.e[1], ev2 = evs.e[2];
   HIPCK(hipEventRecord(ev0, stream));
   if (g.KS != g.K) HIPCK(hipMemsetAsync(A, 0, sizeof(R) * nA, stream));  // padding atoms patch nothing
   HIPCK(hipMemsetAsync(inv_n, 0, sizeof(R) * g.KS, stream));
   if ((rc = run_dtd<R>(ds, stream, g, D, dtd, A, inv_n))) return rc;
   hipLaunchKernelGGL(norms64<R>, dim3(g.K), dim3(256), 0, stream, g.K, g.P * g.L1 * g.L2, D, nrm64);
-  CorrTimer tm_init, tm64;
+  CorrTimer tm_init(evs.e[3], evs.e[4]), tm64(evs.e[5], evs.e[6]);
   int init_prec = DCDL_CORR_F64;
   if (o->warm_start) {
     launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z_out, zpm);
@@ -718,9 +772,6 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
-  (void)hipEventDestroy(ev0);
-  (void)hipEventDestroy(ev1);
-  (void)hipEventDestroy(ev2);
   if (info) {
     std::memset(info, 0, sizeof(*info));
     info->n_updates = (long long)upd;
@@ -796,6 +847,72 @@ int lambda_max_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
   return DCDL_OK;
 }
 
+// Argument checks of dicodile_csc and its no-allocation variant, made before
+// any device access.
+int validate_csc(const dcdl_shape *shape, const void *X, const void *D, const dcdl_csc_opts *opts,
+                 const void *z_out, Geom *g) {
+  int rc = make_geom(shape, g);
+  if (rc) return rc;
+  if (!X || !D || !opts || !z_out) return fail(DCDL_EINVAL, "NULL pointer");
+  if (!(opts->lambda > 0)) return fail(DCDL_EINVAL, "lambda must be > 0");
+  if (!(opts->tol >= 0)) return fail(DCDL_EINVAL, "tol must be >= 0");
+  if (opts->dtype != DCDL_F32 && opts->dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype");
+  if (opts->threads != 0 && !valid_nt(opts->threads))
+    return fail(DCDL_EINVAL, "threads must be 64, 128, 192, 256, 512 or 1024");
+  if (opts->tile[0] < 0 || opts->tile[1] < 0 || opts->grid[0] < 0 || opts->grid[1] < 0)
+    return fail(DCDL_EINVAL, "negative tile or grid");
+  if (opts->max_rounds > (1ll << 30)) return fail(DCDL_EINVAL, "max_rounds above 2^30");
+  if (opts->strategy < DCDL_SELECT_LGCD || opts->strategy > DCDL_SELECT_RANDOM)
+    return fail(DCDL_EINVAL, "unknown selection rule %d", opts->strategy);
+  return DCDL_OK;
+}
+
+// Scratch bytes a solve carves (every workspace slot of csc_impl and the
+// calls it makes, each rounded up to 256 bytes), with the worker count bounded
+// by 8192 workgroups.
+size_t csc_scratch_need(const Geom &g_user, const dcdl_csc_opts *o) {
+  const bool f32 = o->dtype == DCDL_F32;
+  const size_t es = f32 ? 4 : 8;
+  Geom g = g_user;
+  g.KS = atom_stride(g.K, (int)es);
+  auto r = [](size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; };
+  const size_t HW = (size_t)g.H * g.W, nz = HW * g.KS, nA = (size_t)g.K * g.U1 * g.U2 * g.KS;
+  const size_t nW = 8192;
+  size_t need = 2 * r(es * nz) + r(es * HW) + r(4 * HW) + r(es * nA) + r(es * g.K * g.K * g.U1 * g.U2) +
+                r(es * g.KS) + r(8 * (size_t)g.K) + r(16 * nW) + 2 * r(4 * nW) +
+                r(sizeof(Ctl) + sizeof(int) * 2 * kRing) + r(std::max(sizeof(Inst<float>), sizeof(Inst<double>)));
+  need += r(8 * (size_t)g.K * g.P * g.L1 * g.L2) + r(8 * (size_t)g.P * g.T1 * g.T2) + r(64);
+  if (mf_supported(g, MF_F64)) need += r(mf_pack_bytes(g, mf_plan(g, MF_F64), MF_F64));
+  if (!o->warm_start) {
+    const int prec = resolve_prec(o->beta_prec, f32, g);
+    if (prec >= 0 && prec != DCDL_CORR_DIRECT) need += r(mf_pack_bytes(g, mf_plan(g, mf_of(prec)), mf_of(prec)));
+  }
+  return need;
+}
+
+// Once per device, with it current: the device's address of `scratch` and the
+// events of its no-allocation calls.
+int noalloc_setup(DeviceState *ds) {
+  if (ds->scratch_ptr) return DCDL_OK;
+  void *p = nullptr;
+  HIPCK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+  if (!p) return fail(DCDL_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+  for (int i = 0; i < kCallEvents; ++i) HIPCK(hipEventCreate(&ds->na_ev[i]));
+  ds->scratch_ptr = static_cast<unsigned char *>(p);
+  return DCDL_OK;
+}
+
+struct ArenaScope {
+  DeviceState *ds;
+  ScratchArena a;
+  explicit ArenaScope(DeviceState *d) : ds(d) {
+    a.base = d->scratch_ptr;
+    a.cap = kScratchBytes;
+    ds->arena = &a;
+  }
+  ~ArenaScope() { ds->arena = nullptr; }
+};
+
 struct Guard {
   DeviceState *ds;
   explicit Guard(DeviceState *d) : ds(d) { ds->mu.lock(); }
@@ -850,6 +967,14 @@ int dicodile_release(void) {
       if (hipStreamDestroy(ds->aux) != hipSuccess) rc = fail(DCDL_EHIP, "hipStreamDestroy failed");
       ds->aux = nullptr;
     }
+    // the scratch array itself stays (it is part of the loaded code object);
+    // the next no-allocation call looks its address up again
+    for (auto &e : ds->na_ev)
+      if (e) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+      }
+    ds->scratch_ptr = nullptr;
   }
   HIPCK(hipSetDevice(cur));
   return rc;
@@ -894,20 +1019,27 @@ int dicodile_lambda_max(const dcdl_shape *shape, dcdl_dtype dtype, const void *X
 int dicodile_csc(const dcdl_shape *shape, const void *X, const void *D, const dcdl_csc_opts *opts, void *z_out,
                  dcdl_csc_info *info, void *stream_) {
   Geom g;
-  int rc = make_geom(shape, &g);
+  int rc = validate_csc(shape, X, D, opts, z_out, &g);
   if (rc) return rc;
-  if (!X || !D || !opts || !z_out) return fail(DCDL_EINVAL, "NULL pointer");
-  if (!(opts->lambda > 0)) return fail(DCDL_EINVAL, "lambda must be > 0");
-  if (!(opts->tol >= 0)) return fail(DCDL_EINVAL, "tol must be >= 0");
-  if (opts->dtype != DCDL_F32 && opts->dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype");
-  if (opts->threads != 0 && !valid_nt(opts->threads))
-    return fail(DCDL_EINVAL, "threads must be 64, 128, 192, 256, 512 or 1024");
-  if (opts->tile[0] < 0 || opts->tile[1] < 0 || opts->grid[0] < 0 || opts->grid[1] < 0)
-    return fail(DCDL_EINVAL, "negative tile or grid");
-  if (opts->max_rounds > (1ll << 30)) return fail(DCDL_EINVAL, "max_rounds above 2^30");
-  if (opts->strategy < DCDL_SELECT_LGCD || opts->strategy > DCDL_SELECT_RANDOM)
-    return fail(DCDL_EINVAL, "unknown selection rule %d", opts->strategy);
   PROLOGUE();
+  if (opts->dtype == DCDL_F32)
+    return csc_impl<float>(ds, stream, g, shape->ndim, (const float *)X, (const float *)D, opts, (float *)z_out, info);
+  return csc_impl<double>(ds, stream, g, shape->ndim, (const double *)X, (const double *)D, opts, (double *)z_out,
+                          info);
+}
+
+int dicodile_csc_noalloc(const dcdl_shape *shape, const void *X, const void *D, const dcdl_csc_opts *opts,
+                         void *z_out, dcdl_csc_info *info, void *stream_) {
+  Geom g;
+  int rc = validate_csc(shape, X, D, opts, z_out, &g);
+  if (rc) return rc;
+  const size_t need = csc_scratch_need(g, opts);
+  if (need > kScratchBytes)
+    return fail(DCDL_EINVAL, "this solve needs %zu bytes of workspace; the fixed scratch of dicodile_csc_noalloc "
+                "holds %zu", need, kScratchBytes);
+  PROLOGUE();
+  if ((rc = noalloc_setup(ds))) return rc;
+  ArenaScope scope(ds);
   if (opts->dtype == DCDL_F32)
     return csc_impl<float>(ds, stream, g, shape->ndim, (const float *)X, (const float *)D, opts, (float *)z_out, info);
   return csc_impl<double>(ds, stream, g, shape->ndim, (const double *)X, (const double *)D, opts, (double *)z_out,

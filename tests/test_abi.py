@@ -127,6 +127,13 @@ def test_argument_checks_before_device_access(lib):
     rc = lib.dicodile_csc(ctypes.byref(big), ctypes.c_void_p(1), ctypes.c_void_p(1), ctypes.byref(dl.make_opts(-1.0, 0.0, 0)),
                           ctypes.c_void_p(1), ctypes.byref(info), None)
     assert rc == -1 and b"lambda" in lib.dicodile_last_error()
+    # the no-allocation solve refuses a problem beyond its fixed scratch before any device access
+    s2 = dl.Shape()
+    s2.ndim, s2.P, s2.K = 2, 1, 25
+    s2.T[0], s2.T[1], s2.L[0], s2.L[1] = 1024, 1024, 16, 16
+    rc = lib.dicodile_csc_noalloc(ctypes.byref(s2), ctypes.c_void_p(1), ctypes.c_void_p(1),
+                                  ctypes.byref(dl.make_opts(1.0, 0.0, 0)), ctypes.c_void_p(1), ctypes.byref(info), None)
+    assert rc == -1 and b"fixed scratch" in lib.dicodile_last_error()
     # server calls: NULL handles and arguments are rejected before any device access
     assert lib.dicodile_server_create(None, 0, None, None, None) == -1
     assert lib.dicodile_server_submit(None, None, None, None, None, None) == -1
