@@ -71,6 +71,9 @@ def parse():
     ap.add_argument("--budgets", default="0,2048,512",
                     help="serving: HBM admission budgets in MiB to sweep (0: the server default)")
     ap.add_argument("--rate", type=float, default=200.0, help="Poisson arrival rate of the serving workload")
+    ap.add_argument("--rates", default="", help="serving: comma-separated offered rates to sweep (e.g. 200,600,1200)")
+    ap.add_argument("--admit", type=int, default=0,
+                    help="server: workgroups of the admitted requests at most (0: one launch, -1: unbounded)")
     ap.add_argument("--max-workers", type=int, default=0, help="server: workgroups per request at most")
     ap.add_argument("--slice", type=int, default=0, help="server: rounds per launch")
     ap.add_argument("--batch-n", type=int, default=256, help="instances of the batch workload")
@@ -240,6 +243,7 @@ def run_batch(args):
         "max_kkt": max(i["kkt"] for i in infos),
         "batched_phase_ms": {"setup": binfos[-1]["t_setup_s"] * 1e3, "rounds": binfos[-1]["t_rounds_s"] * 1e3,
                              "check": binfos[-1]["t_check_s"] * 1e3},
+        "roofline": _rounds_roofline(infos, binfos[-1]["t_rounds_s"], D.shape[0]),
         "workers": binfos[-1]["workers"], "launches": binfos[-1]["n_passes"],
         "used_graph": binfos[-1]["used_graph"],
         "batch_opts": {k: (list(v) if isinstance(v, tuple) else v) for k, v in bopts.items()},
@@ -249,6 +253,9 @@ def run_batch(args):
         "batched_over_plain": (t_plain / dt) if t_plain else None,
         "generation_s": t_gen,
     }
+    stored = stored_gap("batch_256_images_128-1024_K16_L12")
+    if stored is not None and len(pbs) == 256:
+        out["objective_gap_vs_oracle"] = stored.get("summary")
     print(json.dumps(out), flush=True)
 
 
@@ -259,14 +266,28 @@ def _percentiles(v):
             "mean_ms": float(a.mean() * 1e3), "max_ms": float(a.max() * 1e3)}
 
 
+def _rounds_roofline(infos, t_rounds, K, s_beta=4, s_move=8):
+    """HBM roofline of the round kernel from per-solve counters summed over
+    solves and the round kernel's event time over the same solves."""
+    patched = sum(i["n_patched"] for i in infos)
+    visit_pos = sum(i["n_visits"] * i["tile"][0] * i["tile"][1] for i in infos)
+    checked = sum(i["n_checked"] for i in infos)
+    alg = algorithmic_bytes(patched, visit_pos, checked, K, s_beta, s_move)
+    ach = alg / max(t_rounds, 1e-12) / 1e9
+    return {"bound": "hbm", "kernel": "lgcd_rounds", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": None, "seconds": t_rounds,
+            "counts": {"n_patched": patched, "visit_positions": visit_pos, "n_checked": checked}}
+
+
 def run_serving(args):
     """Serving pattern: Poisson arrivals of multichannel 1-D requests of
     log-uniform length sharing one dictionary, served by continuous batching
-    (dicodile_server_*) under a sweep of HBM admission budgets, beside the
-    plain form: the same arrivals solved one call at a time in arrival order.
-    Latency = arrival -> z ready.  The request signals come from a pool of
-    distinct seeded requests, reused cyclically; every request is solved in
-    full into its own output."""
+    (dicodile_server_*), beside the plain form: the same arrivals solved one
+    call at a time in arrival order.  Latency = arrival -> z ready.  Swept over
+    offered rates (--rates); at the first rate the HBM admission budget is also
+    swept (--budgets).  The request signals come from a pool of distinct
+    seeded requests, reused cyclically; every request is solved in full into
+    its own output."""
     import threading
     import numpy as np
     import torch
@@ -282,18 +303,20 @@ def run_serving(args):
     Xs = [torch.from_numpy(pb.X).to("cuda", dtype=torch.float32).contiguous() for pb in pool]
     lams = [pb.lambda_frac * dl.dicodile_lambda_max(X, D) for pb, X in zip(pool, Xs)]
     L = D.shape[2]
+    K = D.shape[0]
     n_warm, n_meas = args.serve_warmup, args.requests
-    arrivals = synth.serving_arrivals(n_warm + n_meas, rate_hz=args.rate)
-    which = [i % len(pool) for i in range(n_warm + n_meas)]
+    n = n_warm + n_meas
+    which = [i % len(pool) for i in range(n)]
     # one output per in-flight request: a ring deep enough for any backlog here,
     # a multiple of the pool so that slot i % ring always holds signal i % pool
-    ring = len(pool) * max(1, 512 // len(pool))
-    zs = [torch.empty((D.shape[0], Xs[i % len(pool)].shape[1] - L + 1), dtype=torch.float32, device="cuda")
+    ring = len(pool) * max(1, 2048 // len(pool))
+    zs = [torch.empty((K, Xs[i % len(pool)].shape[1] - L + 1), dtype=torch.float32, device="cuda")
           for i in range(ring)]
     torch.cuda.synchronize()
     max_len = max(X.shape[1] for X in Xs)
 
-    def serve(budget_mib):
+    def serve(rate, budget_mib):
+        arrivals = synth.serving_arrivals(n, rate_hz=rate)
         sopts = dict(max_len=max_len)
         if budget_mib > 0:
             sopts["hbm_budget_bytes"] = budget_mib << 20
@@ -301,8 +324,9 @@ def run_serving(args):
             sopts["max_workers"] = args.max_workers
         if args.slice:
             sopts["slice_rounds"] = args.slice
+        if args.admit:
+            sopts["admit_workers"] = args.admit
         srv = dl.Server(D, **sopts)
-        n = n_warm + n_meas
         results, tickets, sub_at = [None] * n, [None] * n, [0.0] * n
         ready = threading.Semaphore(0)
 
@@ -336,28 +360,27 @@ def run_serving(args):
         lat = [(sub_at[i] - (start + arrivals[i])) + results[i]["t_total_s"] for i in meas]
         done = [sub_at[i] + results[i]["t_total_s"] for i in meas]
         span = max(done) - (start + arrivals[n_warm])
-        out = dict(_percentiles(lat), requests_per_s=n_meas / span, budget_mib=budget_mib or "default",
-                   max_kkt=max(results[i]["kkt"] for i in meas),
+        out = dict(_percentiles(lat), requests_per_s=n_meas / span, offered_rate_hz=rate,
+                   budget_mib=budget_mib or "default", max_kkt=max(results[i]["kkt"] for i in meas),
                    queue_p99_ms=_percentiles([results[i]["t_init_s"] for i in meas])["p99_ms"],
                    peak_active=st["peak_active"], peak_workers=st["peak_workers"], launches=st["n_launches"],
-                   rounds_busy_frac=st["t_rounds_s"] / max(1e-9, st["t_busy_s"]))
+                   rounds_busy_frac=st["t_rounds_s"] / max(1e-9, st["t_busy_s"]),
+                   roofline=_rounds_roofline([results[i] for i in range(n)], st["t_rounds_s"], K))
         obj = {which[i]: results[i]["objective"] for i in meas}
-        print(f"# served {n_meas} requests, budget {budget_mib} MiB: {out['requests_per_s']:.1f} req/s, "
-              f"p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        print(f"# served {n_meas} requests at {rate:g}/s, budget {budget_mib} MiB: {out['requests_per_s']:.1f} "
+              f"req/s, p50 {out['p50_ms']:.1f} ms, p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
         return out, obj
 
-    sweeps = [serve(int(b)) for b in args.budgets.split(",")]
-    served, served_obj = sweeps[0]
-
-    # plain form: one dicodile_csc call per request, in arrival order
-    n_plain = n_meas if args.plain < 0 else min(args.plain, n_meas)
-    plain = None
-    gap = 0.0
-    if n_plain > 0:
+    def plain(rate, served_obj):
+        arrivals = synth.serving_arrivals(n, rate_hz=rate)
+        n_plain = n_meas if args.plain < 0 else min(args.plain, n_meas)
+        if n_plain <= 0:
+            return None, 0.0
         for X, lam in zip(Xs[:2], lams[:2]):  # warm-up
             dl.dicodile_csc(X, D, lam, 1e-5 * lam)
         torch.cuda.synchronize()
         plat, pdone = [], []
+        gap = 0.0
         start = time.monotonic() + 0.05
         for i in range(n_plain):
             delay = start + arrivals[i] - time.monotonic()
@@ -372,31 +395,52 @@ def run_serving(args):
             plat.append(now - (start + arrivals[i]))
             pdone.append(now)
             if (i + 1) % 500 == 0:
-                print(f"# plain form: {i + 1} requests", file=sys.stderr, flush=True)
+                print(f"# plain form at {rate:g}/s: {i + 1} requests", file=sys.stderr, flush=True)
             if j in served_obj:
                 gap = max(gap, abs(info["objective"] - served_obj[j]) / info["objective"])
         pspan = pdone[-1] - (start + arrivals[0])
-        plain = dict(_percentiles(plat), requests=n_plain, requests_per_s=n_plain / pspan)
-        print(f"# plain form: {n_plain} requests in {pspan:.2f} s", file=sys.stderr, flush=True)
+        out = dict(_percentiles(plat), requests=n_plain, requests_per_s=n_plain / pspan, offered_rate_hz=rate)
+        print(f"# plain form at {rate:g}/s: {n_plain} requests in {pspan:.2f} s, p50 {out['p50_ms']:.1f} ms, "
+              f"p99 {out['p99_ms']:.1f} ms", file=sys.stderr, flush=True)
+        return out, gap
 
+    rates = [float(r) for r in args.rates.split(",")] if args.rates else [args.rate]
+    budgets = [int(b) for b in args.budgets.split(",")]
+    per_rate = []
+    budget_sweep = []
+    gap = 0.0
+    for ri, rate in enumerate(rates):
+        served, served_obj = serve(rate, budgets[0])
+        if ri == 0:
+            budget_sweep = [served] + [serve(rate, b)[0] for b in budgets[1:]]
+        pl, g = plain(rate, served_obj)
+        gap = max(gap, g)
+        per_rate.append({"offered_rate_hz": rate, "served": served, "plain": pl,
+                         "served_over_plain_throughput": served["requests_per_s"] / pl["requests_per_s"] if pl else None})
+    head = per_rate[0]
     lens = [Xs[j].shape[1] for j in which]
     out = {
         "metric": "served requests/s with p50/p99 latency (arrival -> z at KKT tol), continuous batching vs plain",
-        "value": served["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": n_meas,
-        "warmup": n_warm, "ms_per_step": 1e3 / served["requests_per_s"], "higher_is_better": True,
+        "value": head["served"]["requests_per_s"], "unit": "requests/s", "n_gpus": 1, "steps": n_meas,
+        "warmup": n_warm, "ms_per_step": 1e3 / head["served"]["requests_per_s"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": f"serving_poisson{args.rate:g}_P32_K40_L128_T1e4-5e5",
+        "config": {"workload": f"serving_poisson{rates[0]:g}_P32_K40_L128_T1e4-5e5",
                    "requests": n_meas, "warmup_requests": n_warm, "distinct_signals": len(pool),
-                   "offered_rate_hz": args.rate, "lambda": "0.2 lambda_max each", "tol": "1e-5 lambda each",
+                   "offered_rates_hz": rates, "lambda": "0.2 lambda_max each", "tol": "1e-5 lambda each",
                    "mean_T": float(np.mean(lens))},
-        "served": served,
-        "budget_sweep": [sw for sw, _ in sweeps],
-        "plain": plain,
-        "served_over_plain_throughput": served["requests_per_s"] / plain["requests_per_s"] if plain else None,
-        "max_objective_gap_served_vs_plain": gap if plain else None,
+        "roofline": head["served"]["roofline"],
+        "served": head["served"],
+        "plain": head["plain"],
+        "rates": per_rate,
+        "budget_sweep": budget_sweep,
+        "max_objective_gap_served_vs_plain": gap,
         "generation_s": t_gen,
     }
+    stored = stored_gap("serving_P32_K40_L128_T1e4-5e5")
+    if stored is not None:
+        out["objective_gap_vs_oracle"] = stored.get("summary")
     print(json.dumps(out), flush=True)
+
 
 MFMA_PEAK_TFS = {"f64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0 / 3, "direct": 157.3}
 
@@ -681,6 +725,18 @@ def run_solve(args):
             "peak": 78.6, "unit": "TFLOP/s", "frac": ach / 78.6, "traffic": None,
             "seconds": t64 / args.steps, "launches": n64 / args.steps, "flop_per_launch": fl,
             "mfma_row_fill": K / (16.0 * ((K + 15) // 16))}
+    t_inc = sum(i["t_check_inc_s"] for i in infos)
+    n_inc = sum(i["n_check_inc"] for i in infos)
+    if t_inc > 0:
+        # per changed coordinate: K (2L1-1)(2L2-1) FP64 update-table entries read
+        # and as many FMAs (the changed count comes from the last check of each solve)
+        U = int(np.prod([2 * l - 1 for l in L]))
+        byt = sum(i["n_changed"] for i in infos) * K * U * 8.0
+        kernels["check_inc"] = {
+            "bound": "hbm", "kernel": "g_update_kkt (incremental FP64 check)", "achieved": byt / t_inc / 1e9,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": byt / t_inc / 1e9 / HBM_PEAK_GBS, "traffic": None,
+            "seconds": t_inc / args.steps, "launches": n_inc / args.steps,
+            "changed_coordinates": infos[-1]["n_changed"]}
     dominant = max(kernels, key=lambda k: kernels[k]["seconds"])
     tr = stored_traffic(pb.name, list(infos[-1]["grid"]), list(tile))
     if tr is not None:

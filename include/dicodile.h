@@ -139,6 +139,15 @@ typedef struct {
                              refresh_every = S and refresh_limit = 1 the solve corrects beta once,
                              after S sweeps, and then runs to the certificate */
   uint64_t seed;          /* seed of the RANDOM rule's generator */
+  uint64_t *audit;        /* optional device buffer (dicodile_csc only; NULL = off) of audit_rounds x
+                             W1 x W2 records of the first launch's rounds, for checking the soft-lock
+                             (Prop. A.2): record [r][w] is 0 if worker w (row-major in the worker grid
+                             info->grid) published no candidate in round r; otherwise bit 63 is set,
+                             bit 62 is set if the candidate passed the soft-lock test and was applied,
+                             bits 32..47 hold its atom and bits 0..31 its position h W + w on the valid
+                             domain.  Rounds the launch did not reach keep the caller's contents */
+  int32_t audit_rounds;   /* rounds recorded (from round 0 of the first launch) */
+  int32_t reserved;
 } dcdl_csc_opts;
 
 /* Filled by dicodile_csc when `info` is not NULL (host memory). */
@@ -177,6 +186,12 @@ typedef struct {
                                 and warm start, summed */
   int32_t n_corr64;          /* number of those FP64 contractions */
   int32_t init_prec;         /* dcdl_corr_prec the initialisation ran at (AUTO and fallbacks resolved) */
+  double t_check_inc_s;      /* HIP-event time of the incremental FP64 checks: after a dense FP64
+                                contraction, a later check carries its FP64 gradient and residual
+                                forward over the coordinates changed since (eq. beta_update in FP64)
+                                instead of contracting again, while that is the cheaper path */
+  int32_t n_check_inc;       /* number of those incremental checks */
+  int32_t n_changed;         /* coordinates carried forward by the last incremental check */
 } dcdl_csc_info;
 
 /* Library version string (static storage). */
@@ -393,10 +408,13 @@ typedef struct {
   double t_tune_s;      /* wall time of the call */
   double trial_budget_s;/* round-launch time budget of one trial */
   double obj_default;   /* summed FP64 objective of the sample after one trial budget with tile
-                           2 L, 256 threads and every co-resident workgroup */
-  double obj_best;      /* ... with the chosen configuration (<= obj_default) */
+                           2 L, 256 threads and every co-resident workgroup (mean of two runs) */
+  double obj_best;      /* ... with the chosen configuration (<= obj_default); a configuration
+                           other than the default is chosen only when it is lower by more than
+                           3 obj_spread */
   int32_t cached;       /* 1: answered from the per-process cache, nothing timed */
   int32_t reserved;
+  double obj_spread;    /* |difference| of the default's two runs: the run-to-run noise */
 } dcdl_tune_info;
 
 /* Autotuner of dicodile_csc_batch.  Runs candidate configurations on a
@@ -446,7 +464,11 @@ typedef struct {
   int32_t threads;          /* threads per worker workgroup (64, 128, 192, 256); 0 -> 256 */
   int32_t tile[2];          /* sub-domain size; 0 -> 2 L_i (d = 1: tile[0] is the length) */
   int32_t max_polish;       /* extra passes for requests failing the final check; 0 -> 2 */
-  int32_t reserved;
+  int32_t admit_workers;    /* admission stops while the admitted requests' workgroups would exceed
+                               this (the first request is always admitted); 0 -> the co-resident
+                               capacity of one launch, so the admitted set advances together in
+                               one launch; -1 -> no bound (only lanes and memory limit admission).
+                               Launch slots go to the oldest ready requests first */
 } dcdl_server_opts;
 
 /* Counters of a server since its creation (host memory). */

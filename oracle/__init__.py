@@ -77,7 +77,7 @@ def _load():
     lib.orc_beta.argtypes = shp + [_dp, _dp, _dp, _dp]
     lib.orc_lgcd.argtypes = shp + [_dp, _dp, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                    ctypes.c_int, ctypes.c_int, _i64, ctypes.c_int, ctypes.c_int,
-                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp,
+                                   ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp, _dp,
                                    ctypes.POINTER(LgcdInfo)]
     lib.orc_lgcd.restype = ctypes.c_int
     lib.orc_dicodile_z.argtypes = shp + [_dp, _dp, ctypes.c_double, ctypes.c_double,
@@ -215,11 +215,13 @@ def _default_tile(L1, L2, is_1d):
 
 def lgcd(X, D, lam: float, tol: float, positive: bool = False, tile=None,
          max_sweeps: int = 10 ** 9, z0=None, certify: bool = True, check_every: int = 0,
-         kkt_every: int = 0, kkt_target: float = 1e-4):
+         kkt_every: int = 0, kkt_target: float = 1e-4, beta0=None):
     """Sequential LGCD (Alg. 1).  Returns (Z, info dict).
 
     certify=True makes support- and sign-changing moves score at least tol
-    (the certifying stop rule); certify=False is the plain |Delta Z| rule."""
+    (the certifying stop rule); certify=False is the plain |Delta Z| rule.
+    z0 warm-starts the sweeps; beta0 (with z0) is beta of z0 computed by the
+    caller (e.g. ``beta_fft``), used instead of the direct FP64 loops."""
     X3, D4, is_1d = _as2d(X, D)
     s = _shape(X3, D4)
     P, T1, T2, K, L1, L2 = s
@@ -228,11 +230,14 @@ def lgcd(X, D, lam: float, tol: float, positive: bool = False, tile=None,
     elif np.isscalar(tile):
         tile = (1, int(tile)) if is_1d else (int(tile), int(tile))
     Z = np.zeros(_zshape(*s)) if z0 is None else _in_z(z0, _zshape(*s), is_1d).copy()
+    if beta0 is not None and z0 is None:
+        raise ValueError("beta0 needs the iterate z0 it belongs to")
+    b0 = None if beta0 is None else _in_z(beta0, _zshape(*s), is_1d)
     info = LgcdInfo()
     rc = _load().orc_lgcd(*s, _p(X3), _p(D4), float(lam), float(tol), int(positive),
                           int(tile[0]), int(tile[1]), int(max_sweeps), int(z0 is not None),
-                          int(certify), int(check_every), int(kkt_every), float(kkt_target), _p(Z),
-                          ctypes.byref(info))
+                          int(certify), int(check_every), int(kkt_every), float(kkt_target),
+                          None if b0 is None else _p(b0), _p(Z), ctypes.byref(info))
     if rc != 0:
         raise ValueError("orc_lgcd rejected its arguments")
     d = {f: getattr(info, f) for f, _ in LgcdInfo._fields_ if f != "pad"}

@@ -267,6 +267,8 @@ typedef struct {
  * sweeps.
  *
  * warm_start = 1 takes Z as the initial iterate; otherwise Z starts at 0.
+ * beta0, when not NULL, is beta of that initial iterate (its definition in
+ * Sec. 3, computed by the caller) and replaces the direct computation.
  * check_every > 0 recomputes beta from its definition every check_every
  * sweeps and records the drift of the incremental beta (beta itself is not
  * replaced).  kkt_every > 0 evaluates the strict KKT violation every
@@ -276,7 +278,7 @@ int orc_lgcd(int P, int64_t T1, int64_t T2, int K, int L1, int L2,
              const double *X, const double *D, double lambda, double tol,
              int positive, int tile1, int tile2, int64_t max_sweeps,
              int warm_start, int certify, int check_every, int kkt_every,
-             double kkt_target, double *Z, orc_lgcd_info *info) {
+             double kkt_target, const double *beta0, double *Z, orc_lgcd_info *info) {
   if (P < 1 || K < 1 || L1 < 1 || L2 < 1 || T1 < L1 || T2 < L2 || tile1 < 1 || tile2 < 1 ||
       !(lambda > 0.0) || tol < 0.0)
     return -1;
@@ -293,7 +295,10 @@ int orc_lgcd(int P, int64_t T1, int64_t T2, int K, int L1, int L2,
   orc_atom_norms(K, P, L1, L2, D, n);
   orc_dtd(K, P, L1, L2, D, C);
   if (!warm_start) memset(Z, 0, sizeof(double) * (size_t)nz);
-  orc_beta(P, T1, T2, K, L1, L2, X, D, Z, beta);
+  if (beta0)
+    memcpy(beta, beta0, sizeof(double) * (size_t)nz);
+  else
+    orc_beta(P, T1, T2, K, L1, L2, X, D, Z, beta);
 
   memset(info, 0, sizeof(*info));
   info->t_kkt_s = -1.0;

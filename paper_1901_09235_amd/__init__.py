@@ -53,7 +53,8 @@ class CscOpts(ctypes.Structure):
                 ("inner", ctypes.c_int32), ("beta_prec", ctypes.c_int32), ("max_rounds", ctypes.c_int64),
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
                 ("kkt_target", ctypes.c_double), ("strategy", ctypes.c_int32),
-                ("refresh_limit", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("refresh_limit", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("audit", ctypes.c_void_p), ("audit_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class CscInfo(ctypes.Structure):
@@ -71,7 +72,8 @@ class CscInfo(ctypes.Structure):
                 ("t_worker_select_s", ctypes.c_double), ("t_worker_collect_s", ctypes.c_double),
                 ("t_worker_apply_s", ctypes.c_double), ("beta_drift", ctypes.c_double),
                 ("t_init_corr_s", ctypes.c_double), ("t_corr64_s", ctypes.c_double),
-                ("n_corr64", ctypes.c_int32), ("init_prec", ctypes.c_int32)]
+                ("n_corr64", ctypes.c_int32), ("init_prec", ctypes.c_int32),
+                ("t_check_inc_s", ctypes.c_double), ("n_check_inc", ctypes.c_int32), ("n_changed", ctypes.c_int32)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -79,7 +81,7 @@ class ServerOpts(ctypes.Structure):
                 ("max_workers", ctypes.c_int32), ("slice_rounds", ctypes.c_int32),
                 ("max_active", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("tile", ctypes.c_int32 * 2), ("max_polish", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("admit_workers", ctypes.c_int32)]
 
 
 class ServerStats(ctypes.Structure):
@@ -262,7 +264,9 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
               div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0,
-              beta_prec=0, strategy=0, seed=0, refresh_limit=0) -> CscOpts:
+              beta_prec=0, strategy=0, seed=0, refresh_limit=0, audit=None) -> CscOpts:
+    """dcdl_csc_opts from keyword options; audit is an int64 device tensor of
+    (rounds, W1 * W2) receiving the round log of the first launch."""
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -284,6 +288,12 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
             raise DicodileError(-1, f"unknown selection rule {strategy!r} (one of {sorted(SELECT)})")
         strategy = SELECT[strategy]
     o.strategy, o.seed = int(strategy), int(seed) & (2 ** 64 - 1)
+    if audit is not None:
+        torch = _torch()
+        _device_tensor(audit, "audit")
+        if audit.dtype != torch.int64 or audit.dim() != 2:
+            raise DicodileError(-1, "audit must be an int64 device tensor (rounds, workers)")
+        o.audit, o.audit_rounds = audit.data_ptr(), int(audit.shape[0])
     return o
 
 
@@ -500,7 +510,8 @@ class BatchInfo(ctypes.Structure):
 class TuneInfo(ctypes.Structure):
     _fields_ = [("n_trials", ctypes.c_int32), ("n_sample", ctypes.c_int32), ("t_tune_s", ctypes.c_double),
                 ("trial_budget_s", ctypes.c_double), ("obj_default", ctypes.c_double),
-                ("obj_best", ctypes.c_double), ("cached", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("obj_best", ctypes.c_double), ("cached", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("obj_spread", ctypes.c_double)]
 
 
 def _batch_args(Xs, D, lams, tols, opts):
@@ -613,7 +624,7 @@ class Server:
     interpreter exit are closed then."""
 
     def __init__(self, D, hbm_budget_bytes=0, max_len=0, max_workers=0, slice_rounds=0,
-                 max_active=0, threads=0, tile=None, max_polish=0):
+                 max_active=0, threads=0, tile=None, max_polish=0, admit_workers=0):
         lib = load()
         _device_tensor(D, "D")
         self.dtype_code = _dtype_code(D)
@@ -631,7 +642,7 @@ class Server:
         o = ServerOpts()
         o.hbm_budget_bytes, o.max_len = int(hbm_budget_bytes), int(max_len)
         o.max_workers, o.slice_rounds, o.max_active = int(max_workers), int(slice_rounds), int(max_active)
-        o.threads, o.max_polish = int(threads), int(max_polish)
+        o.threads, o.max_polish, o.admit_workers = int(threads), int(max_polish), int(admit_workers)
         if tile is not None:
             t = (tile, 0) if isinstance(tile, int) else tuple(tile)
             o.tile[0], o.tile[1] = int(t[0]), int(t[1])

@@ -24,6 +24,7 @@
 #include "dcdl_kernels.h"
 #include "dcdl_mfma.h"
 #include "dcdl_dict.h"
+#include "dcdl_check.h"
 
 using namespace dcdl;
 
@@ -387,7 +388,7 @@ template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
             int positive, double *obj, double *kkt, long long *nnz, const R *beta_cmp = nullptr,
             const double *nrm64 = nullptr, double *drift = nullptr, R *beta_fix = nullptr,
-            CorrTimer *tm = nullptr) {
+            CorrTimer *tm = nullptr, double *g64 = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -407,6 +408,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.nrm = nrm64;
   o.result2 = scal + 4;
   o.beta = beta_fix;
+  o.g64 = g64;
   void *pk64;
   if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
   if (tm && (rc = tm->begin(stream))) return rc;
@@ -428,7 +430,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
 // With fresh = false it reuses the residual and D64 left by check64.
 template <class R>
 int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
-                  const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr) {
+                  const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr, double *g64 = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -444,6 +446,7 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   ob.beta = beta;
   ob.zpm = zpm;
   ob.nrm = nrm64;
+  ob.g64 = g64;
   void *pk64;
   int rc = pack64<R>(ds, stream, g, D, &pk64);
   if (rc) return rc;
@@ -451,6 +454,88 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   rc = corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
   if (rc || !tm) return rc;
   return tm->end(stream);
+}
+
+// The incremental FP64 check (dcdl_check.h) of a position-major z against the
+// reference (gref, zref, the residual in the "res64" slot) left by the last
+// dense FP64 contraction or incremental check, which it advances to z.  Needs
+// D in FP64 in the "D64" slot.  Sets *used = false, changing nothing, when the
+// number of changed coordinates exceeds `max_changes` (the dense contraction is
+// then cheaper).  Also rebuilds beta = g + n z in `beta`.
+template <class R>
+int check_inc(DeviceState *ds, hipStream_t stream, const Geom &g, const R *zpm, double *gref, R *zref,
+              const double *nrm64, double lambda, int positive, long long max_changes, R *beta, double *obj,
+              double *kkt, long long *nnz, double *drift, bool *used, long long *n_changed) {
+  *used = false;
+  const long long HW = (long long)g.H * g.W, nx = (long long)g.P * g.T1 * g.T2;
+  const int KS64 = atom_stride(g.K, 8);
+  const long long nA64 = (long long)g.K * g.U1 * g.U2 * KS64;
+  const int ntr = (g.H + kChkTH - 1) / kChkTH, ntc = (g.W + kChkTW - 1) / kChkTW;
+  const long long ntiles = (long long)ntr * ntc;
+  const long long per_change = ((long long)(g.U1 + kChkTH - 1) / kChkTH + 1) * ((g.U2 + kChkTW - 1) / kChkTW + 1);
+  double *D64, *res, *scal, *A64, *dtd64, *inv64;
+  Change *chg;
+  unsigned long long *cnt;
+  unsigned *tcnt, *toff, *tcur, *tlist;
+  WS("D64", sizeof(double) * (size_t)g.K * g.P * g.L1 * g.L2, D64);
+  WS("res64", sizeof(double) * nx, res);
+  WS("scal", 64, scal);
+  WS("chk_count", 16, cnt);
+  WS("chk_changes", sizeof(Change) * (size_t)std::max(1ll, max_changes), chg);
+  HIPCK(hipMemsetAsync(cnt, 0, 8, stream));
+  HIPCK(hipMemsetAsync(scal, 0, 64, stream));
+  hipLaunchKernelGGL((diff_changes<R>), dim3(grid_stride_blocks(HW * g.KS)), dim3(256), 0, stream, HW, g.K, g.KS,
+                     zpm, zref, chg, cnt, max_changes, scal + 2);
+  unsigned long long nch = 0;
+  HIPCK(hipMemcpyAsync(&nch, cnt, 8, hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  *n_changed = (long long)nch;
+  if ((long long)nch > max_changes) return DCDL_OK;
+  *used = true;
+  // the FP64 update table A64[k0][d1][d2][k] (padding atoms zero)
+  Geom g64 = g;
+  g64.KS = KS64;
+  WS("A64", sizeof(double) * nA64, A64);
+  WS("dtd64", sizeof(double) * (size_t)g.K * g.K * g.U1 * g.U2, dtd64);
+  WS("inv64", sizeof(double) * KS64, inv64);
+  if (KS64 != g.K) HIPCK(hipMemsetAsync(A64, 0, sizeof(double) * nA64, stream));
+  int rc = run_dtd<double>(ds, stream, g64, D64, dtd64, A64, inv64);
+  if (rc) return rc;
+  WS("chk_tiles", sizeof(unsigned) * (3 * (size_t)ntiles + 1), tcnt);
+  toff = tcnt + ntiles;
+  tcur = toff + ntiles + 1;
+  WS("chk_list", sizeof(unsigned) * (size_t)std::max(1ll, (long long)nch * per_change), tlist);
+  if (nch > 0) {
+    const unsigned nb = (unsigned)std::min<long long>((long long)nch, 65536);
+    hipLaunchKernelGGL(residual_scatter, dim3(nb), dim3(256), 0, stream, g, chg, (long long)nch, D64, res);
+    HIPCK(hipMemsetAsync(tcnt, 0, sizeof(unsigned) * ntiles, stream));
+    hipLaunchKernelGGL(bin_count, dim3(grid_stride_blocks((long long)nch)), dim3(256), 0, stream, g, chg,
+                       (long long)nch, ntc, tcnt);
+    hipLaunchKernelGGL(bin_scan, dim3(1), dim3(1024), 0, stream, tcnt, ntiles, toff, tcur);
+    hipLaunchKernelGGL(bin_fill, dim3(grid_stride_blocks((long long)nch)), dim3(256), 0, stream, g, chg,
+                       (long long)nch, ntc, tcur, tlist);
+  } else {
+    HIPCK(hipMemsetAsync(toff, 0, sizeof(unsigned) * (ntiles + 1), stream));
+  }
+  IncOut io{};
+  io.lambda = lambda;
+  io.positive = positive;
+  io.nrm = nrm64;
+  io.result = scal + 4;
+  io.beta_cmp = beta;
+  io.beta = beta;
+  hipLaunchKernelGGL((g_update_kkt<R>), dim3((unsigned)ntiles), dim3(256), 0, stream, g, chg, toff, tlist, A64,
+                     KS64, ntc, gref, zpm, zref, io);
+  hipLaunchKernelGGL(sum_squares, dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res, scal);
+  HIPCK(hipGetLastError());
+  double h[6];
+  HIPCK(hipMemcpyAsync(h, scal, 48, hipMemcpyDeviceToHost, stream));
+  HIPCK(hipStreamSynchronize(stream));
+  *obj = 0.5 * h[0] + lambda * h[2];
+  *kkt = h[4] / lambda;
+  *nnz = (long long)h[3];
+  *drift = h[5] / lambda;
+  return DCDL_OK;
 }
 
 // Exact FP64 norms from D.
@@ -675,6 +760,28 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   const int refresh = o->refresh_every > 0 ? o->refresh_every : 0;
   const int refresh_limit = o->refresh_limit > 0 ? o->refresh_limit : 0;
   int n_refresh = 0;
+  // FP64 reference of the incremental check: g and z of the last dense FP64
+  // contraction (its residual stays in the "res64" slot).  Not used by the
+  // no-allocation entry point, whose scratch holds the dense path only.
+  const bool inc_ok = ds->arena == nullptr;
+  bool have_ref = false;
+  double *gref = nullptr;
+  R *zref = nullptr;
+  // the incremental check pays while the changed coordinates' patches,
+  // K (2L1-1)(2L2-1) FP64 table entries each, cost under half the dense
+  // contraction's 2 (16 ceil(K/16)) P L1 L2 flops per position (rates of the
+  // two paths on gfx950: about 6 TB/s of table reads, 55 TFLOP/s of FP64 MFMA)
+  const double dense_s = 2.0 * 16 * ((g.K + 15) / 16) * g.P * g.L1 * g.L2 * (double)HW / 55e12;
+  const long long max_changes = std::max(1ll, std::min((long long)(0.5 * dense_s * 6e12 / (8.0 * g.K * g.U1 * g.U2)),
+                                                       HW * g.K));
+  CorrTimer tm_inc(evs.e[3], evs.e[4]);
+  long long n_changed = 0;
+  auto want_ref = [&]() -> int {
+    if (!inc_ok || gref) return DCDL_OK;
+    WS("gref", sizeof(double) * nz, gref);
+    WS("zref", sizeof(R) * nz, zref);
+    return DCDL_OK;
+  };
   long long rounds_left = o->max_rounds > 0 ? o->max_rounds : (1ll << 30);
   double t_cd = 0, t_check = 0, obj = 0, kkt = 0;
   long long nnz = 0;
@@ -696,6 +803,9 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       if (o->timeout_s > 0) budget = std::max(1e-3, o->timeout_s - (now_s() - t_start));
       hi.budget_ticks = (long long)(budget * 1e8);
     }
+    // the round log covers the first launch only
+    hi.audit = passes == 1 ? reinterpret_cast<unsigned long long *>(o->audit) : nullptr;
+    hi.audit_rounds = passes == 1 && o->audit ? std::max(0, o->audit_rounds) : 0;
     HIPCK(hipMemcpyAsync(d_inst, &hi, sizeof(hi), hipMemcpyHostToDevice, stream));
     HIPCK(hipMemsetAsync(prog, 0, sizeof(int) * nW, stream));
     // all-ones tags carry a round number no launch reaches
@@ -740,7 +850,12 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       // (A coarser contraction here would re-inject errors above tol at every
       // chunk, and the sweep certificate could never be reached.)
       ++n_refresh;
-      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64))) return rc;
+      if ((rc = want_ref())) return rc;
+      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, gref))) return rc;
+      if (gref) {
+        HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
+        have_ref = true;
+      }
       launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
       HIPCK(hipStreamSynchronize(stream));
       t_check += now_s() - tc0;
@@ -750,9 +865,23 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     // beta); the same contraction rebuilds beta from its FP64 definition for a
     // polish pass
     double drift_now = 0;
-    rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now,
-                    beta, &tm64);
-    if (rc) return rc;
+    bool inc_used = false;
+    if (have_ref) {
+      if ((rc = tm_inc.begin(stream))) return rc;
+      rc = check_inc<R>(ds, stream, g, zpm, gref, zref, nrm64, o->lambda, o->positive, max_changes, beta, &obj, &kkt,
+                        &nnz, &drift_now, &inc_used, &n_changed);
+      if (rc) return rc;
+      if (inc_used) {
+        if ((rc = tm_inc.end(stream))) return rc;
+      }
+    }
+    if (!inc_used) {
+      if ((rc = want_ref())) return rc;
+      rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now,
+                      beta, &tm64, gref);
+      if (rc) return rc;
+      have_ref = false;
+    }
     if (n_checks++ == 0) beta_drift = drift_now;
     if (sweep_done && kkt <= kkt_target) {
       t_check += now_s() - tc0;
@@ -764,7 +893,12 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       t_check += now_s() - tc0;
       break;
     }
-    // another pass: beta was rebuilt from its FP64 definition by the check
+    // another pass: beta was rebuilt from its FP64 definition by the check,
+    // which is the reference of the next one
+    if (!inc_used && gref) {
+      HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
+      have_ref = true;
+    }
     launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
     HIPCK(hipStreamSynchronize(stream));
     t_check += now_s() - tc0;
@@ -805,6 +939,9 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     info->t_corr64_s = tm64.s;
     info->n_corr64 = tm64.n;
     info->init_prec = init_prec;
+    info->t_check_inc_s = tm_inc.s;
+    info->n_check_inc = tm_inc.n;
+    info->n_changed = (int32_t)std::min<long long>(n_changed, INT32_MAX);
   }
   return status;
 }

@@ -100,7 +100,21 @@ template <class R> struct Inst {
   // start of a launch and stored at its end, so that a solve split over
   // several launches (each capped by max_rounds) keeps its stopping state
   long long *wstate;
+  // optional round log: for rounds r < audit_rounds, audit[r * W1 W2 + w]
+  // records worker w's published candidate (audit_record)
+  unsigned long long *audit;
+  int audit_rounds;
 };
+
+// A worker's published candidate of one round: 0 when it had none; otherwise
+// bit 63 set, bit 62 set if it passed the soft-lock test (and was applied),
+// the atom in bits 32..47 and the position (row-major in the valid domain)
+// in bits 0..31.
+__device__ __forceinline__ unsigned long long audit_record(bool has, bool accepted, int k0, int pos) {
+  if (!has) return 0ull;
+  return (1ull << 63) | ((accepted ? 1ull : 0ull) << 62) | ((unsigned long long)(k0 & 0xffff) << 32) |
+         (unsigned long long)(unsigned)pos;
+}
 
 // ----------------------------------------------------------------- arithmetic
 
@@ -935,6 +949,8 @@ __device__ void run_worker(const Inst<R> &I, const int w, const long long timeou
           }
         }
       }
+      if (I.audit && r < I.audit_rounds)
+        I.audit[(long long)r * nW + w] = audit_record(has, has && !locked, sm.ck0, bp);
       st_shared_u64(I.cand + 2 * w + 1, dbits);
       wait_vm();
       st_shared_u64(I.cand + 2 * w, tag);

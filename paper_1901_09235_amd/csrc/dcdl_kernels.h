@@ -105,6 +105,7 @@ struct CorrOut {
   double *result;      // CORR_KKT: max violation; CORR_ABSMAX: max |G| (one-sided if positive)
   const void *beta_cmp;  // CORR_KKT, optional: a maintained beta (H, W, KS) in Rz compared with
   double *result2;       //   G + n z (needs nrm); result2 receives the max absolute difference
+  double *g64;           // CORR_KKT and CORR_BETA, optional: G in FP64, (H, W, KS), atoms < K only
 };
 
 template <class Rin, class Racc, class Rz, int MODE, int KC, int TH>
@@ -148,6 +149,7 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
       for (int q = 0; q < KC; ++q) {
         if (q >= kc) break;
         const int k = kb + q;
+        if (MODE != CORR_ABSMAX && o.g64) o.g64[pos * g.KS + k] = (double)acc[q];
         if (MODE == CORR_BETA) {
           double v = (double)acc[q];
           if (o.zpm) v += o.nrm[k] * (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];

@@ -141,7 +141,10 @@ __device__ __forceinline__ void mf_load_b(const typename MfT<PREC>::In *p, typen
 // TR x (4 NTW 16 / TR) positions per workgroup: TR = 1 for signals (the four
 // waves side by side along the row), TR = 4 for images (one row per wave).
 // PC = 0 takes the channel chunk from the plan (FP64, one element per lane).
-template <int PREC, int MODE, int TR, int NTW, int MT, int PC, class Rin, class Rz>
+// TALL: the window of every t1 is staged once per channel chunk, TR + L1 - 1
+// rows (row wr + t1 serves wave wr at tap row t1), instead of TR rows per t1;
+// the steps of consecutive t1 then run without a barrier between them.
+template <int PREC, int MODE, int TR, int NTW, int MT, int PC, bool TALL, class Rin, class Rz>
 __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *__restrict__ X,
                                                  const typename MfT<PREC>::In *__restrict__ Dpk, long long npk,
                                                  int m0, CorrOut o) {
@@ -155,7 +158,8 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
   const int pcs = PC > 0 ? PC : pl.PC;
   const int TCX = TC + pl.L2p;  // staged columns
   const int row_elems = TCX * pcs;
-  const int copy_elems = TR * row_elems;
+  const int nrows = TALL ? TR + g.L1 - 1 : TR;  // staged rows
+  const int copy_elems = nrows * row_elems;
   __shared__ double sh_red[4];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -170,28 +174,34 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
 #pragma unroll
     for (int n = 0; n < NTW; ++n) acc[m][n] = typename T::C4{0, 0, 0, 0};
 
-  for (int t1 = 0; t1 < g.L1; ++t1)
-    for (int pc = 0; pc < pl.NPC; ++pc) {
-      __syncthreads();
-      // stage rows h0 + t1 + r, columns w0 + c, channels pc PC + pp
-      for (int e = tid; e < copy_elems; e += 256) {
-        const int c = e % TCX, rest = e / TCX;
-        const int pp = rest % pcs, r = rest / pcs;
-        const int p = pc * pcs + pp, hh = h0 + t1 + r, ww = w0 + c;
-        double v = 0.0;
-        if (p < g.P && hh < g.T1 && ww < g.T2) v = (double)X[p * plane + (long long)hh * g.T2 + ww];
-        const int li = r * row_elems + c * pcs + pp;
-        if constexpr (PREC == MF_F64) {
-          xs[li] = (In)v;
-        } else {
-          const __bf16 hi = (__bf16)(float)v;
-          xs[li] = hi;
-          if constexpr (T::NCOPY == 2) xs[copy_elems + li] = (__bf16)((float)v - (float)hi);
+  for (int pcq = 0; pcq < pl.NPC; ++pcq)
+    for (int t1q = 0; t1q < g.L1; ++t1q) {
+      // the non-TALL order is (t1, chunk); TALL runs every t1 of a chunk
+      const int t1 = TALL ? t1q : (pcq * g.L1 + t1q) / pl.NPC;
+      const int pc = TALL ? pcq : (pcq * g.L1 + t1q) % pl.NPC;
+      if (!TALL || t1 == 0) {
+        __syncthreads();
+        // stage rows h0 + (TALL ? 0 : t1) + r, columns w0 + c, channels pc PC + pp
+        const int hbase = h0 + (TALL ? 0 : t1);
+        for (int e = tid; e < copy_elems; e += 256) {
+          const int c = e % TCX, rest = e / TCX;
+          const int pp = rest % pcs, r = rest / pcs;
+          const int p = pc * pcs + pp, hh = hbase + r, ww = w0 + c;
+          double v = 0.0;
+          if (p < g.P && hh < g.T1 && ww < g.T2) v = (double)X[p * plane + (long long)hh * g.T2 + ww];
+          const int li = r * row_elems + c * pcs + pp;
+          if constexpr (PREC == MF_F64) {
+            xs[li] = (In)v;
+          } else {
+            const __bf16 hi = (__bf16)(float)v;
+            xs[li] = hi;
+            if constexpr (T::NCOPY == 2) xs[copy_elems + li] = (__bf16)((float)v - (float)hi);
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
       const long long sbase = ((long long)(t1 * pl.NPC + pc) * pl.SPS) * pl.MTT;
-      const In *xrow = xs + wr * row_elems;
+      const In *xrow = xs + (wr + (TALL ? t1 : 0)) * row_elems;
       for (int s = 0; s < pl.SPS; ++s) {
         In a[T::NCOPY][MT][VPL];
 #pragma unroll
@@ -244,6 +254,7 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
       for (int v = 0; v < 4; ++v) {
         const int k = 16 * (m0 + m) + (PREC == MF_F64 ? (lane >> 4) + 4 * v : 4 * (lane >> 4) + v);
         const double gv = (double)acc[m][n][v];
+        if (MODE != CORR_ABSMAX && o.g64 && k < g.K) o.g64[pos * g.KS + k] = gv;
         if (MODE == CORR_BETA) {
           if (k < g.K) {
             double bv = gv;

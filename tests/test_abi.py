@@ -60,7 +60,8 @@ int main(void) {
   printf("%zu %zu\\n", sizeof(dcdl_tune_info), offsetof(dcdl_csc_info, beta_drift));
   printf("%zu %zu %d\\n", offsetof(dcdl_csc_opts, strategy), offsetof(dcdl_csc_opts, seed), (int)DCDL_SELECT_RANDOM);
   printf("%zu %zu %zu %zu\\n", offsetof(dcdl_csc_opts, refresh_limit), offsetof(dcdl_csc_info, t_init_corr_s),
-         offsetof(dcdl_csc_info, n_corr64), offsetof(dcdl_csc_info, init_prec));
+         offsetof(dcdl_csc_info, n_corr64), offsetof(dcdl_csc_info, n_changed));
+  printf("%zu %zu\\n", offsetof(dcdl_csc_opts, audit), offsetof(dcdl_csc_opts, audit_rounds));
   return 0;
 }
 """)
@@ -87,7 +88,9 @@ int main(void) {
     assert sel == [dl.CscOpts.strategy.offset, dl.CscOpts.seed.offset, dl.SELECT["random"]]
     tail = [int(v) for v in lines[7].split()]
     assert tail == [dl.CscOpts.refresh_limit.offset, dl.CscInfo.t_init_corr_s.offset, dl.CscInfo.n_corr64.offset,
-                    dl.CscInfo.init_prec.offset]
+                    dl.CscInfo.n_changed.offset]
+    aud = [int(v) for v in lines[8].split()]
+    assert aud == [dl.CscOpts.audit.offset, dl.CscOpts.audit_rounds.offset]
 
 
 def test_argument_checks_before_device_access(lib):

@@ -115,8 +115,11 @@ def test_autotuned_batch_matches_oracle_and_is_cached(lib):
     Dd = dev(D, torch.float32)
     tols = [1e-5 * l for l in lams]
     kw, info = lib.dicodile_csc_batch_autotune(Xs, Dd, lams, tols)
-    assert info["cached"] == 0 and info["n_trials"] == 6 and 1 <= info["n_sample"] <= 8
-    assert info["obj_best"] <= info["obj_default"]
+    assert info["cached"] == 0 and info["n_trials"] == 7 and 1 <= info["n_sample"] <= 8
+    assert info["obj_best"] <= info["obj_default"] and info["obj_spread"] >= 0
+    # a configuration other than the default wins only by more than 3x the noise
+    if kw["threads"] != 256 or kw["tile"][0] != 2 * D.shape[2] or kw.get("workers", 0):
+        assert info["obj_default"] - info["obj_best"] > 3 * info["obj_spread"]
     assert kw["threads"] in (128, 256)
     assert kw["tile"][0] in (9, 12, 18, 24) and kw["tile"][1] in (9, 12, 18, 24)
     kw2, info2 = lib.dicodile_csc_batch_autotune(Xs, Dd, lams, tols)

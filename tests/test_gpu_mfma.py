@@ -175,8 +175,9 @@ def test_single_drift_correction_after_bf16_start(lib):
                                beta_prec="bf16", refresh_every=2, refresh_limit=1, grid=(3, 3), timeout_s=60)
     assert info["status"] == "OK", info
     assert info["init_prec"] == 2 and info["t_init_corr_s"] > 0
-    # the one correction, then one check per pass after it
-    assert info["n_corr64"] == info["n_passes"], info
+    # the one correction (a dense FP64 contraction), then one check per pass
+    # after it, each carried forward from the correction's FP64 gradient
+    assert info["n_corr64"] == 1 and info["n_check_inc"] == info["n_passes"] - 1, info
     assert info["t_corr64_s"] > 0
     Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
     fo = oracle.objective(X, Dd, Zo, lam)
@@ -188,8 +189,9 @@ def test_single_drift_correction_after_bf16_start(lib):
 def test_failed_check_rebuilds_beta_in_the_same_contraction(lib):
     """A check that fails (here: a BF16 start and no earlier correction, so
     the first pass converges on a perturbed beta) rebuilds beta from the FP64
-    contraction it has just run: every pass costs one FP64 contraction, and
-    the polished result meets the oracle."""
+    contraction it has just run, and the polish pass's check is carried
+    forward from it: one FP64 contraction for the whole solve, and the
+    polished result meets the oracle."""
     D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(13)), 5, 2, 40)
     pb = synth.make_problem("p", 905, P=2, T=8000, K=5, L=40, rho=0.005, amp="exp", sigma=0.1, D=D)
     X = pb.X.astype(np.float32).astype(np.float64)
@@ -198,9 +200,40 @@ def test_failed_check_rebuilds_beta_in_the_same_contraction(lib):
     z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
                                beta_prec="bf16", grid=6, max_polish=4, timeout_s=60)
     assert info["status"] == "OK", info
-    assert info["n_corr64"] == info["n_passes"], info
+    # the first (dense) check fails and is the FP64 reference of the polish
+    # pass's check, which carries its gradient forward
+    assert info["n_passes"] >= 2 and info["n_corr64"] == 1, info
+    assert info["n_check_inc"] == info["n_passes"] - 1, info
     Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam)
     fo = oracle.objective(X, Dd, Zo, lam)
     Zg = z.double().cpu().numpy()
     assert (oracle.objective(X, Dd, Zg, lam) - fo) / fo <= 1e-6
     assert oracle.kkt(X, Dd, Zg, lam) <= 1e-4
+
+
+@pytest.mark.parametrize("positive", [False, True])
+def test_incremental_check_equals_the_dense_check(lib, positive):
+    """After the one drift correction, the final check carries that FP64
+    contraction's gradient and residual forward over the coordinates changed
+    since (info n_check_inc); its objective and strict KKT equal a dense FP64
+    check of the returned z (dicodile_objective_kkt) and the oracle's."""
+    D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(14)), 7, 2, (9, 7))
+    pb = synth.make_problem("p", 906, P=2, T=(90, 77), K=7, L=(9, 7), rho=0.004, amp="exp", sigma=0.05, D=D)
+    X = pb.X.astype(np.float32).astype(np.float64)
+    Dd = D.astype(np.float32).astype(np.float64)
+    lam = 0.1 * oracle.lambda_max(X, Dd, positive=positive)
+    Xt, Dt = dev(X, torch.float32), dev(Dd, torch.float32)
+    z, info = lib.dicodile_csc(Xt, Dt, lam, 1e-5 * lam, positive=positive, beta_prec="bf16", refresh_every=2,
+                               refresh_limit=1, grid=(3, 3), timeout_s=60)
+    assert info["status"] == "OK", info
+    assert info["n_check_inc"] >= 1 and info["t_check_inc_s"] > 0, info
+    assert info["n_corr64"] == 1, info  # the drift correction only
+    f_dense, k_dense = lib.dicodile_objective_kkt(Xt, Dt, z, lam, positive=positive)
+    assert info["objective"] == pytest.approx(f_dense, rel=1e-10)
+    assert info["kkt"] == pytest.approx(k_dense, rel=1e-6, abs=1e-10)
+    Zg = z.double().cpu().numpy()
+    assert oracle.objective(X, Dd, Zg, lam) == pytest.approx(info["objective"], rel=1e-9)
+    assert oracle.kkt(X, Dd, Zg, lam, positive=positive) == pytest.approx(info["kkt"], rel=1e-6, abs=1e-10)
+    Zo, _ = oracle.lgcd(X, Dd, lam, 1e-10 * lam, positive=positive)
+    fo = oracle.objective(X, Dd, Zo, lam)
+    assert (info["objective"] - fo) / fo <= 1e-6
