@@ -84,6 +84,7 @@ def parse():
     ap.add_argument("--grid", type=int, nargs="*", default=None)
     ap.add_argument("--tile", type=int, nargs="*", default=None)
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--inner", type=int, default=0, help="sub-domain visits per worker per round (0: 1)")
     ap.add_argument("--no-autotune", action="store_true", help="batch: skip the autotuner (defaults)")
     ap.add_argument("--ablation-cap", type=float, default=30.0,
                     help="ablation: wall-clock cap of one solve in seconds")
@@ -210,6 +211,14 @@ def run_batch(args):
     for _ in range(args.warmup):
         dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs, **bopts)
     torch.cuda.synchronize()
+    t_default = None
+    if tune is not None and (tuple(bopts.get("tile", ())) != (2 * D.shape[2], 2 * D.shape[3])
+                             or bopts.get("threads", 256) != 256 or bopts.get("workers", 0)):
+        # the default configuration beside the tuned one (outside the timed region)
+        t0 = time.perf_counter()
+        _, _, bd = dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs)
+        torch.cuda.synchronize()
+        t_default = time.perf_counter() - t0
     binfos, t0 = [], time.perf_counter()
     for _ in range(args.steps):
         _, infos, binfo = dl.dicodile_csc_batch(Xs, D, lams, tols, z_outs=zs, **bopts)
@@ -248,6 +257,7 @@ def run_batch(args):
         "used_graph": binfos[-1]["used_graph"],
         "batch_opts": {k: (list(v) if isinstance(v, tuple) else v) for k, v in bopts.items()},
         "autotune": tune,
+        "default_config_s": t_default,
         "plain_s_for_all": t_plain,
         "plain_instances_timed": n_plain,
         "batched_over_plain": (t_plain / dt) if t_plain else None,
@@ -646,6 +656,8 @@ def run_solve(args):
         opts["tile"] = tuple(args.tile) if len(args.tile) > 1 else args.tile[0]
     if args.threads:
         opts["threads"] = args.threads
+    if args.inner:
+        opts["inner"] = args.inner
 
     copy_gbs = None
     if args.probe_mib > 0:
@@ -739,8 +751,10 @@ def run_solve(args):
             "changed_coordinates": infos[-1]["n_changed"]}
     dominant = max(kernels, key=lambda k: kernels[k]["seconds"])
     tr = stored_traffic(pb.name, list(infos[-1]["grid"]), list(tile))
-    if tr is not None:
-        kernels["lgcd_rounds"]["traffic"] = tr["bytes_per_launch"]
+    if tr is not None and tr.get("fix_after") == fix_after and tr.get("beta_init") == init_prec:
+        # HBM bytes of the round kernel's launches in one step, as the algorithmic
+        # bytes_per_step are counted
+        kernels["lgcd_rounds"]["traffic"] = tr["bytes_per_step"]
         kernels["lgcd_rounds"]["traffic_source"] = tr["source"]
     last = infos[-1]
     t_solve = sum(i["t_total_s"] for i in infos) / args.steps

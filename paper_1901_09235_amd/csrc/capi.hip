@@ -1230,7 +1230,8 @@ int dicodile_copy_probe(void *dst, const void *src, size_t bytes, int32_t repeat
     return fail(DCDL_EINVAL, "copy probe needs 16-byte aligned, non-empty buffers and repeats >= 1");
   PROLOGUE();
   const long long n16 = (long long)(bytes / 16);
-  const unsigned nb = (unsigned)std::min<long long>((n16 + 255) / 256, (long long)ds->cus * 16);
+  if ((n16 + 255) / 256 > 0x7fffffffll) return fail(DCDL_EINVAL, "copy probe of more than 2^39 bytes");
+  const unsigned nb = (unsigned)((n16 + 255) / 256);
   hipEvent_t e0, e1;
   HIPCK(hipEventCreate(&e0));
   HIPCK(hipEventCreate(&e1));
