@@ -507,6 +507,66 @@ def run_corr_bench(args):
         res[name] = {"gflop": flop / 1e9, "precisions": out}
         del X, D
         torch.cuda.empty_cache()
+    # the dense formulation of the dictionary statistics on the RGB workload:
+    # phi[k, k', tau] = sum_w Z_k[w] Z_k'[w + tau] is, per lag tau, a K x K
+    # product over all valid positions, and there are (2L1-1)(2L2-1) lags.  One
+    # such product (contiguous operands: no shift copies, so a lower bound) is
+    # timed with the vendor GEMM and scaled to every lag; the library computes
+    # phi from the non-zeros instead (dict_stats_ms on the headline line).
+    K, H, W, L = 25, 4065, 4065, 32
+    lags = (2 * L - 1) ** 2
+    dense = {"lags": lags, "positions": H * W, "flop_per_lag": 2.0 * K * K * H * W}
+    for name, dt in (("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        A = torch.randn((K, H * W), generator=gen, device="cuda", dtype=torch.float32).to(dt)
+        B = torch.randn((H * W, K), generator=gen, device="cuda", dtype=torch.float32).to(dt)
+        C = A @ B  # warm-up
+        torch.cuda.synchronize()
+        st = torch.cuda.current_stream()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(5):
+            C = A @ B
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 5
+        dense[name] = {"gemm_ms": ms, "tflops": dense["flop_per_lag"] / (ms * 1e-3) / 1e12,
+                       "projected_phi_ms": ms * lags}
+        print(f"# dense phi lag product {name}: {ms:.3f} ms per lag, {ms * lags:.0f} ms for all lags",
+              file=sys.stderr, flush=True)
+        del A, B, C
+        torch.cuda.empty_cache()
+    # the library's nnz-driven form on a z of the workload's recipe
+    # (Bernoulli(5e-4) x Exp(1) on 25 x 4065^2): its time and its useful flops
+    # (2 per non-zero pair within a lag window for phi, 2 P L1 L2 per non-zero
+    # for psi), beside the dense form's flops at the dtype peaks
+    Z = (torch.rand((K, H, W), generator=gen, device="cuda") < 5e-4).float()
+    Z *= -torch.log(torch.rand((K, H, W), generator=gen, device="cuda"))
+    X = torch.randn((3, 4096, 4096), generator=gen, device="cuda", dtype=torch.float32)
+    nzc = (Z != 0).sum(dim=0).float()
+    box = torch.nn.functional.avg_pool2d(nzc[None, None], 2 * L - 1, stride=1, padding=L - 1,
+                                         count_include_pad=True)[0, 0] * float((2 * L - 1) ** 2)
+    pairs = float((nzc.double() * box.round().double()).sum())
+    nnz = int(nzc.sum())
+    dl.dicodile_dict_stats(Z, X, (L, L))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        dl.dicodile_dict_stats(Z, X, (L, L))
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / 3 * 1e3
+    useful = 2.0 * pairs + 2.0 * nnz * 3 * L * L
+    dense_flop = dense["flop_per_lag"] * lags + 2.0 * K * 3 * L * L * H * W
+    dense["nnz_form"] = {"nnz": nnz, "pairs_within_window": pairs, "useful_gflop": useful / 1e9, "ms": ms,
+                         "useful_tflops": useful / (ms * 1e-3) / 1e12}
+    dense["dense_form_tflop"] = dense_flop / 1e12
+    dense["dense_floor_ms"] = {k: dense_flop / (MFMA_PEAK_TFS[k] * 1e12) * 1e3 for k in ("bf16", "f64")}
+    dense["dense_floor_ms"]["fp32_vector"] = dense_flop / 157.3e12 * 1e3
+    for name in ("fp32", "bf16"):
+        dense[name]["useful_tflops_projected"] = useful / (dense[name]["projected_phi_ms"] * 1e-3) / 1e12
+    print(f"# nnz-driven ztz/ztX: {ms:.2f} ms, {nnz} non-zeros, {pairs:.3g} pairs, "
+          f"{useful / (ms * 1e-3) / 1e9:.1f} useful GFLOP/s", file=sys.stderr, flush=True)
+    del Z, X
+    res["dense_phi_rgb_4096"] = dense
     best = res["serving_max_P32_T500000_K40_L128"]["precisions"]["f64"]
     line = {
         "metric": "dense correlation corr(X, D) throughput on the matrix cores", "value": best["tflops"],

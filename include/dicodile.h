@@ -212,7 +212,11 @@ int dicodile_release(void);
 /* DtD (Sec. 3, the kernel of eq. beta_update):
  *   dtd[k0][k][tau + L - 1] = sum_p sum_t D_{k0,p}[t] D_{k,p}[t + tau],
  *   tau in Phi = [-L+1, L-1]^d.
- * D: (K, P, L...) device, dtype.  dtd_out: (K, K, 2L1-1[, 2L2-1]) device, dtype. */
+ * D: (K, P, L...) device, dtype.  dtd_out: (K, K, 2L1-1[, 2L2-1]) device, dtype.
+ * Computed in FP64 on the matrix cores (one correlation of D with an image of
+ * the atoms laid side by side, zero-padded), or by direct FP64 loops for
+ * atoms whose staged windows exceed the matrix-core LDS budget; rounded once
+ * to dtype. */
 int dicodile_dtd(const dcdl_shape *shape, dcdl_dtype dtype, const void *D, void *dtd_out,
                  void *stream);
 

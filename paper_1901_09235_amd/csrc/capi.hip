@@ -257,8 +257,10 @@ struct CorrTimer {
 };
 
 // ------------------------------------------------------------- kernels
+// DtD by the direct FP64 loops (atoms whose staged windows do not fit the
+// matrix-core path).
 template <class R>
-int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *dtd, R *A, R *inv_n) {
+int run_dtd_loops(hipStream_t stream, const Geom &g, const R *D, R *dtd, R *A, R *inv_n) {
   const size_t lds = 2 * sizeof(R) * (size_t)g.P * g.L1 * g.L2;
   if (lds > 160 * 1024) return fail(DCDL_EINVAL, "atoms of %d values exceed the LDS budget", g.P * g.L1 * g.L2);
   hipLaunchKernelGGL(dtd_kernel<R>, dim3(g.K * g.K), dim3(256), lds, stream, g, D, dtd, A, inv_n);
@@ -283,6 +285,64 @@ int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, cons
 #include "mfma_host.inc"
 
 int mf_of(int prec) { return prec == DCDL_CORR_F64 ? MF_F64 : (prec == DCDL_CORR_BF16 ? MF_BF16 : MF_BF16X3); }
+
+// ------------------------------------------------------------- DtD
+// Geometry of the DtD image (dtd_image) and whether the FP64 matrix cores
+// take its correlation.
+bool dtd_geom(const Geom &g, Geom *gi) {
+  *gi = g;
+  gi->T1 = 3 * g.L1 - 2;
+  gi->H = g.U1;
+  gi->W = g.K * g.U2;
+  gi->T2 = gi->W + g.L2 - 1;
+  gi->KS = g.K;
+  return (long long)g.K * g.U2 + g.L2 < (1ll << 30) && mf_supported(*gi, MF_F64);
+}
+
+struct DtdWs {
+  size_t img, pk, G;
+  size_t total() const { return img + pk + G; }
+};
+
+DtdWs dtd_ws_bytes(const Geom &gi) {
+  auto r = [](size_t b) { return (b + 255) / 256 * 256; };
+  DtdWs w;
+  w.img = r(8 * (size_t)gi.P * gi.T1 * gi.T2);
+  w.pk = r(mf_pack_bytes(gi, mf_plan(gi, MF_F64), MF_F64));
+  w.G = r(8 * (size_t)gi.H * gi.W * gi.KS);
+  return w;
+}
+
+// DtD, the apply table and 1/||D_k||^2 as one FP64 matrix-core correlation
+// of the DtD image, in the caller's workspace of dtd_ws_bytes(gi).total()
+// bytes.
+template <class R>
+int run_dtd_mfma(hipStream_t stream, const Geom &g, const Geom &gi, const R *D, R *dtd, R *A, R *inv_n, void *ws) {
+  const DtdWs w = dtd_ws_bytes(gi);
+  double *img = (double *)ws, *G = (double *)((char *)ws + w.img + w.pk);
+  void *pk = (char *)ws + w.img;
+  const long long nimg = (long long)gi.P * gi.T1 * gi.T2;
+  hipLaunchKernelGGL(dtd_image<R>, dim3(grid_stride_blocks(nimg)), dim3(256), 0, stream, gi, D, img, nimg);
+  const MfPlan pl = mf_plan(gi, MF_F64);
+  int rc = mf_pack<R>(stream, gi, pl, MF_F64, D, pk);
+  if (rc) return rc;
+  CorrOut o{};
+  o.beta = G;
+  if ((rc = run_corr_mfma<MF_F64, CORR_BETA, double, double>(stream, gi, pl, img, pk, o))) return rc;
+  const long long n = (long long)g.K * g.U1 * g.U2 * g.K;
+  hipLaunchKernelGGL(dtd_gather<R>, dim3(grid_stride_blocks(n)), dim3(256), 0, stream, g, G, dtd, A, inv_n, n);
+  HIPCK(hipGetLastError());
+  return DCDL_OK;
+}
+
+template <class R>
+int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *dtd, R *A, R *inv_n) {
+  Geom gi;
+  if (!dtd_geom(g, &gi)) return run_dtd_loops<R>(stream, g, D, dtd, A, inv_n);
+  void *ws;
+  WS("dtd_ws", dtd_ws_bytes(gi).total(), ws);
+  return run_dtd_mfma<R>(stream, g, gi, D, dtd, A, inv_n, ws);
+}
 
 // The contraction actually used for a requested dcdl_corr_prec on data of
 // type R: AUTO picks BF16X3 for FP32 and F64 for FP64; the matrix-core
@@ -1019,6 +1079,8 @@ size_t csc_scratch_need(const Geom &g_user, const dcdl_csc_opts *o) {
                 r(es * g.KS) + r(8 * (size_t)g.K) + r(16 * nW) + 2 * r(4 * nW) +
                 r(sizeof(Ctl) + sizeof(int) * 2 * kRing) + r(std::max(sizeof(Inst<float>), sizeof(Inst<double>)));
   need += r(8 * (size_t)g.K * g.P * g.L1 * g.L2) + r(8 * (size_t)g.P * g.T1 * g.T2) + r(64);
+  Geom gi;
+  if (dtd_geom(g, &gi)) need += r(dtd_ws_bytes(gi).total());
   if (mf_supported(g, MF_F64)) need += r(mf_pack_bytes(g, mf_plan(g, MF_F64), MF_F64));
   if (!o->warm_start) {
     const int prec = resolve_prec(o->beta_prec, f32, g);

@@ -86,6 +86,49 @@ __global__ __launch_bounds__(256) void dtd_kernel(Geom g, const R *__restrict__ 
   }
 }
 
+// ------------------------------------------------ DtD on the matrix cores
+// DtD is itself a correlation with D.  Lay the atoms side by side along the
+// second axis, atom k0 at columns k0 U2 + L2 - 1 ... k0 U2 + 2 L2 - 2 and rows
+// L1 - 1 ... 2 L1 - 2, zeros elsewhere (the L - 1 zeros between neighbours
+// serve both); this image has 3 L1 - 2 rows and K U2 + L2 - 1 columns.  Its
+// valid correlation with D (U1 rows, K U2 columns) is, at row a1 and column
+// k0 U2 + a2, sum_t D_k[t] D_k0[t + (a1, a2) - (L - 1)]: the apply-table entry
+// A[k0][a1][a2][k], i.e. dtd[k0][k] at lag (L - 1) - (a1, a2).
+template <class R>
+__global__ __launch_bounds__(256) void dtd_image(Geom gi, const R *__restrict__ D, double *__restrict__ img,
+                                                 long long n) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const int a2 = (int)(i % gi.T2);
+    const long long q = i / gi.T2;
+    const int a1 = (int)(q % gi.T1), p = (int)(q / gi.T1);
+    const int t1 = a1 - (gi.L1 - 1), c = a2 - (gi.L2 - 1);
+    double v = 0.0;
+    if (t1 >= 0 && t1 < gi.L1 && c >= 0) {
+      const int k0 = c / gi.U2, t2 = c - k0 * gi.U2;
+      if (k0 < gi.K && t2 < gi.L2) v = (double)D[(((long long)k0 * gi.P + p) * gi.L1 + t1) * gi.L2 + t2];
+    }
+    img[i] = v;
+  }
+}
+
+// dtd, the apply table (atom stride g.KS, padding left as set by the caller)
+// and 1/||D_k||^2 from G = corr(dtd_image, D) stored (U1, K U2, K).
+template <class R>
+__global__ __launch_bounds__(256) void dtd_gather(Geom g, const double *__restrict__ G, R *__restrict__ dtd,
+                                                  R *__restrict__ A, R *__restrict__ inv_n, long long n) {
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    const int k = (int)(i % g.K);
+    long long q = i / g.K;
+    const int a2 = (int)(q % g.U2);
+    q /= g.U2;
+    const int a1 = (int)(q % g.U1), k0 = (int)(q / g.U1);
+    const double v = G[(((long long)a1 * g.K + k0) * g.U2 + a2) * g.K + k];
+    A[(((long long)k0 * g.U1 + a1) * g.U2 + a2) * g.KS + k] = (R)v;
+    dtd[(((long long)k0 * g.K + k) * g.U1 + (g.U1 - 1 - a1)) * g.U2 + (g.U2 - 1 - a2)] = (R)v;
+    if (k == k0 && a1 == g.L1 - 1 && a2 == g.L2 - 1) inv_n[k] = (R)(1.0 / v);
+  }
+}
+
 // ------------------------------------------------------------- correlation
 // G[pos][k] = sum_p sum_t D[k,p,t] X[p, pos + t] on the valid domain, computed
 // directly: one thread per output position, KC atoms at a time, the slice

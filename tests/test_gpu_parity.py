@@ -44,12 +44,25 @@ def _small_signal(seed, T=900, K=3, L=32, P=2, rho=0.01):
 
 # ----------------------------------------------------------------- operators
 
+def _unit_atoms(seed, shape):
+    D = np.random.default_rng(seed).standard_normal(shape)
+    return D / np.sqrt((D.reshape(shape[0], -1) ** 2).sum(axis=1)).reshape((-1,) + (1,) * (len(shape) - 1))
+
+
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
-@pytest.mark.parametrize("case", ["img", "sig", "rgb"])
+@pytest.mark.parametrize("case", ["img", "sig", "rgb", "rgb_k20", "sig_k40", "sig_long"])
 def test_dtd_matches_oracle(lib, dtype, case):
-    pb = {"img": _small_image(1), "sig": _small_signal(2), "rgb": _small_image(3, P=3, L=(5, 7))}[case]
-    C = host(lib.dicodile_dtd(dev(pb.D, dtype)))
-    ref = oracle.dtd(pb.D)
+    """DtD against the oracle's loops: the matrix-core form (two 16-atom
+    tiles for K = 20 and 40, several column tiles per atom), and the direct
+    loops for atoms whose staged windows exceed the matrix-core LDS budget
+    (8 channels x 1000 taps)."""
+    D = {"img": lambda: _small_image(1).D, "sig": lambda: _small_signal(2).D,
+         "rgb": lambda: _small_image(3, P=3, L=(5, 7)).D,
+         "rgb_k20": lambda: _unit_atoms(7, (20, 3, 16, 24)),
+         "sig_k40": lambda: _unit_atoms(8, (40, 4, 128)),
+         "sig_long": lambda: _unit_atoms(9, (3, 8, 1000))}[case]()
+    C = host(lib.dicodile_dtd(dev(D, dtype)))
+    ref = oracle.dtd(D)
     tol = 1e-12 if dtype == torch.float64 else 1e-6
     np.testing.assert_allclose(C, ref, rtol=0, atol=tol * np.abs(ref).max())
 
