@@ -66,7 +66,11 @@ typedef enum {
   DCDL_CORR_BF16 = 2,    /* v_mfma_f32_16x16x32_bf16: BF16 operands, FP32 sums (FP32 data only) */
   DCDL_CORR_BF16X3 = 3,  /* the same on hi/lo BF16 splits (hi*hi + hi*lo + lo*hi), about FP32
                             accuracy (FP32 data only) */
-  DCDL_CORR_DIRECT = 4   /* vector FMA in the data's precision, no matrix cores */
+  DCDL_CORR_DIRECT = 4,  /* vector FMA in the data's precision, no matrix cores */
+  DCDL_CORR_F64_FFT = 5  /* FP64 by FFT (the correlation theorem over the powers of two covering
+                            T1 x T2): images whose padded sizes lie in [64, 8192] with P <= 8;
+                            otherwise, or if its workspace (about 16 (K P + P + K) N1 N2 / 2
+                            bytes) does not fit in 60% of free device memory, F64 */
 } dcdl_corr_prec;
 
 /* Coordinate-selection rule of the solve (dcdl_csc_opts.strategy).  Sec. 3
@@ -147,7 +151,10 @@ typedef struct {
                              bits 32..47 hold its atom and bits 0..31 its position h W + w on the valid
                              domain.  Rounds the launch did not reach keep the caller's contents */
   int32_t audit_rounds;   /* rounds recorded (from round 0 of the first launch) */
-  int32_t reserved;
+  int32_t fp64_method;    /* how the FP64 contractions (drift corrections, checks, warm start) run:
+                             0 -> by FFT where DCDL_CORR_F64_FFT applies and its estimated time is
+                             below the FP64 matrix cores', 1 -> FP64 matrix cores only, 2 -> by FFT
+                             wherever it applies.  The arithmetic is FP64 either way */
 } dcdl_csc_opts;
 
 /* Filled by dicodile_csc when `info` is not NULL (host memory). */
@@ -169,7 +176,7 @@ typedef struct {
   int32_t grid[2];        /* worker grid used */
   int32_t tile[2];        /* sub-domain size used */
   int32_t n_passes;       /* solve passes (1 + polish passes) */
-  int32_t reserved;
+  int32_t n_fft64;        /* FP64 contractions that ran by FFT (the initialisation included) */
   int64_t n_visits;       /* sub-domain visits (worker rounds with a sub-domain to scan) */
   int64_t n_checked;      /* positions read by soft-lock tests */
   int64_t n_patched;      /* positions of beta patched by accepted updates */

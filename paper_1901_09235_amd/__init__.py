@@ -28,7 +28,8 @@ _lib = None
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "PENDING", -1: "EINVAL", -2: "ENOMEM", -3: "EHIP",
           -4: "EDIVERGED", -5: "ETIMEOUT", -6: "ENODEV"}
 F32, F64 = 0, 1
-CORR_PREC = {"auto": 0, "f64": 1, "bf16": 2, "bf16x3": 3, "direct": 4}
+CORR_PREC = {"auto": 0, "f64": 1, "bf16": 2, "bf16x3": 3, "direct": 4, "f64_fft": 5}
+FP64_METHOD = {"auto": 0, "mfma": 1, "fft": 2}
 SELECT = {"lgcd": 0, "greedy": 1, "cyclic": 2, "random": 3}
 
 
@@ -54,7 +55,7 @@ class CscOpts(ctypes.Structure):
                 ("div_guard", ctypes.c_double), ("timeout_s", ctypes.c_double),
                 ("kkt_target", ctypes.c_double), ("strategy", ctypes.c_int32),
                 ("refresh_limit", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("audit", ctypes.c_void_p), ("audit_rounds", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("audit", ctypes.c_void_p), ("audit_rounds", ctypes.c_int32), ("fp64_method", ctypes.c_int32)]
 
 
 class CscInfo(ctypes.Structure):
@@ -66,7 +67,7 @@ class CscInfo(ctypes.Structure):
                 ("t_init_s", ctypes.c_double), ("t_cd_s", ctypes.c_double),
                 ("t_check_s", ctypes.c_double), ("converged", ctypes.c_int32),
                 ("grid", ctypes.c_int32 * 2), ("tile", ctypes.c_int32 * 2),
-                ("n_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_passes", ctypes.c_int32), ("n_fft64", ctypes.c_int32),
                 ("n_visits", ctypes.c_int64), ("n_checked", ctypes.c_int64),
                 ("n_patched", ctypes.c_int64), ("t_worker_wait_s", ctypes.c_double),
                 ("t_worker_select_s", ctypes.c_double), ("t_worker_collect_s", ctypes.c_double),
@@ -264,9 +265,10 @@ def dicodile_lambda_max(X, D, positive: bool = False, stream=None) -> float:
 def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=True, grid=None,
               tile=None, threads=0, warm_start=False, refresh_every=0, max_polish=0, max_rounds=0,
               div_guard=0.0, timeout_s=0.0, kkt_target=0.0, no_soft_lock=False, inner=0,
-              beta_prec=0, strategy=0, seed=0, refresh_limit=0, audit=None) -> CscOpts:
+              beta_prec=0, strategy=0, seed=0, refresh_limit=0, audit=None, fp64_method=0) -> CscOpts:
     """dcdl_csc_opts from keyword options; audit is an int64 device tensor of
-    (rounds, W1 * W2) receiving the round log of the first launch."""
+    (rounds, W1 * W2) receiving the round log of the first launch;
+    fp64_method is "auto", "mfma" or "fft" (or its code)."""
     o = CscOpts()
     o.lambda_, o.tol = float(lam), float(tol)
     o.positive, o.certify, o.dtype = int(positive), int(certify), int(dtype_code)
@@ -288,6 +290,11 @@ def make_opts(lam: float, tol: float, dtype_code: int, positive=False, certify=T
             raise DicodileError(-1, f"unknown selection rule {strategy!r} (one of {sorted(SELECT)})")
         strategy = SELECT[strategy]
     o.strategy, o.seed = int(strategy), int(seed) & (2 ** 64 - 1)
+    if isinstance(fp64_method, str):
+        if fp64_method not in FP64_METHOD:
+            raise DicodileError(-1, f"unknown FP64 method {fp64_method!r} (one of {sorted(FP64_METHOD)})")
+        fp64_method = FP64_METHOD[fp64_method]
+    o.fp64_method = int(fp64_method)
     if audit is not None:
         torch = _torch()
         _device_tensor(audit, "audit")
@@ -354,7 +361,7 @@ def _csc_call(fn: str, X, D, lam: float, tol: float, z_out, stream, opts):
 
 def dicodile_corr(X, D, prec="auto", out=None, stream=None):
     """G = corr(X, D) on the valid domain, shape (K, T-L+1 ...), in X's dtype.
-    prec: "auto", "f64", "bf16", "bf16x3" or "direct" (dcdl_corr_prec)."""
+    prec: "auto", "f64", "bf16", "bf16x3", "direct" or "f64_fft" (dcdl_corr_prec)."""
     torch = _torch()
     lib = load()
     _device_tensor(X, "X")

@@ -25,6 +25,7 @@
 #include "dcdl_mfma.h"
 #include "dcdl_dict.h"
 #include "dcdl_check.h"
+#include "dcdl_fft.h"
 
 using namespace dcdl;
 
@@ -286,6 +287,204 @@ int run_corr(hipStream_t stream, const Geom &g, const Rin *X, const Rin *D, cons
 
 int mf_of(int prec) { return prec == DCDL_CORR_F64 ? MF_F64 : (prec == DCDL_CORR_BF16 ? MF_BF16 : MF_BF16X3); }
 
+// ------------------------------------------------------------- FP64 by FFT
+// Transform sizes of the FFT contraction (dcdl_fft.h): images whose powers of
+// two covering T1 and T2 lie in [64, 8192] (a row transform fits the LDS), at
+// most 8 channels.
+bool fft_geom(const Geom &g, FftGeom *f) {
+  if (g.P > 8 || g.T1 > 8192 || g.T2 > 8192) return false;
+  int N1 = 1, N2 = 1;
+  while (N1 < g.T1) N1 <<= 1;
+  while (N2 < g.T2) N2 <<= 1;
+  if (N1 < 64 || N2 < 64) return false;
+  f->N1 = N1;
+  f->N2 = N2;
+  f->M2 = N2 / 2;
+  f->F2p = (f->M2 + 1 + 15) / 16 * 16;
+  if (N1 > 128) {
+    f->B = 64;
+    f->A = N1 / 64;
+  } else {
+    f->A = N1;
+    f->B = 1;
+  }
+  f->plane = (long long)N1 * f->F2p;
+  return true;
+}
+
+// An atom's spectrum skips its first column pass when its L1 rows fit in one
+// row block of the second.
+bool fft_atoms_sparse(const Geom &g, const FftGeom &f) { return g.L1 <= (f.B > 1 ? f.B : f.N1); }
+
+struct FftWs {
+  size_t tw, dhat, e, rhat, shat, G;
+  size_t total() const { return tw + dhat + e + rhat + shat + G; }
+};
+
+// Workspace of the FFT contraction with inverse transforms kc atoms at a time.
+FftWs fft_ws(const Geom &g, const FftGeom &f, int kc) {
+  auto r = [](size_t b) { return (std::max<size_t>(b, 256) + 255) / 256 * 256; };
+  const size_t sp = 16 * (size_t)f.plane;
+  FftWs w;
+  w.tw = r(16 * (size_t)(f.N1 + f.N2));
+  w.dhat = r(sp * g.K * g.P);
+  w.e = fft_atoms_sparse(g, f) ? r(16 * (size_t)g.K * g.P * g.L1 * f.F2p) : 0;
+  w.rhat = r(sp * g.P);
+  w.shat = r(sp * kc);
+  w.G = r(8 * (size_t)g.K * g.H * g.W);
+  return w;
+}
+
+// Estimated seconds of one FP64 contraction: on the matrix cores (FP64 MFMA
+// at about 55 TFLOP/s with 16-atom tiles) and by FFT (the HBM bytes of its
+// passes at about 4.5 TB/s, dictionary spectra included).
+double mfma64_seconds(const Geom &g) {
+  return 2.0 * 16 * ((g.K + 15) / 16) * g.P * g.L1 * g.L2 * (double)g.H * g.W / 55e12;
+}
+
+double fft64_seconds(const Geom &g, const FftGeom &f) {
+  const double sp = 16.0 * f.plane, hw = (double)g.H * g.W;
+  double b = (double)g.K * g.P * sp;                         // dictionary spectra (one write)
+  b += g.P * (8.0 * g.T1 * g.T2 + 5 * sp);                   // rows, two column passes
+  b += sp * (g.P + (double)g.K * g.P + g.K);                 // products
+  b += g.K * (5 * sp + 8.0 * hw);                            // inverse passes, rows
+  b += 8.0 * g.K * hw + 16.0 * hw * g.KS;                    // epilogue
+  return b / 4.5e12;
+}
+
+size_t ws_held(DeviceState *ds, const char *name) {
+  auto it = ds->bufs.find(name);
+  return it == ds->bufs.end() ? 0 : it->second.n;
+}
+
+// The FP64 contractions of one call: how they are computed (0: FFT where it
+// is estimated faster, 1: matrix cores only, 2: FFT wherever supported) and
+// whether the "fft_dhat" slot holds the spectra of the call's dictionary.
+struct Fp64Ctx {
+  int method = 0;
+  bool dhat_ok = false;
+  const void *dhat = nullptr;
+  int n_fft = 0;
+};
+
+// Whether an FP64 contraction of g runs by FFT under `method`, and the atom
+// chunk of its inverse transforms (the workspace is kept within 60% of the
+// device memory free to the library).
+bool fft64_pick(DeviceState *ds, const Geom &g, int method, FftGeom *f, int *kc) {
+  if (ds->arena || method == 1 || !fft_geom(g, f)) return false;
+  if (method == 0 && fft64_seconds(g, *f) >= mfma64_seconds(g)) return false;
+  size_t fr = 0, tot = 0;
+  if (hipMemGetInfo(&fr, &tot) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  size_t avail = fr;
+  for (const char *n : {"fft_tw", "fft_dhat", "fft_e", "fft_rhat", "fft_shat", "fft_g"}) avail += ws_held(ds, n);
+  for (int c = g.K;; c = (c + 1) / 2) {
+    if (fft_ws(g, *f, c).total() <= avail / 10 * 6) {
+      *kc = c;
+      return true;
+    }
+    if (c == 1) return false;
+  }
+}
+
+// M-point column transforms (fft_cols) of nb spectra of S: groups g of rows
+// g gmul + i stride; see ColArgs.
+void fft_cols_m(int M, hipStream_t st, const FftGeom &f, double2 *S, int nb, int ngroups, int gmul, int stride,
+                int rows_valid, int rows_store, int inverse, int twiddle, const double2 *tw1,
+                const double2 *E = nullptr, long long eb = 0, int e_rows = 0) {
+  const ColArgs ca{f, S, ngroups, gmul, stride, rows_valid, rows_store, inverse, twiddle, tw1, E, eb, e_rows};
+  const int gpw = 128 / M;
+  const dim3 grid(f.F2p / 16, (ngroups + gpw - 1) / gpw, nb), blk(256);
+  switch (M) {
+    case 4: hipLaunchKernelGGL(fft_cols<4>, grid, blk, 0, st, ca); break;
+    case 8: hipLaunchKernelGGL(fft_cols<8>, grid, blk, 0, st, ca); break;
+    case 16: hipLaunchKernelGGL(fft_cols<16>, grid, blk, 0, st, ca); break;
+    case 32: hipLaunchKernelGGL(fft_cols<32>, grid, blk, 0, st, ca); break;
+    case 64: hipLaunchKernelGGL(fft_cols<64>, grid, blk, 0, st, ca); break;
+    default: hipLaunchKernelGGL(fft_cols<128>, grid, blk, 0, st, ca); break;
+  }
+}
+
+// Forward column transforms of nb spectra whose input rows >= rows_valid are
+// zero (digit-swapped output order), and their inverse back to natural order
+// writing rows < rows_store.
+void fft_cols_forward(hipStream_t st, const FftGeom &f, double2 *S, int nb, int rows_valid, const double2 *tw1) {
+  if (f.B > 1) {
+    fft_cols_m(f.A, st, f, S, nb, f.B, 1, f.B, rows_valid, f.N1, 0, 1, tw1);
+    fft_cols_m(f.B, st, f, S, nb, f.A, f.B, 1, f.N1, f.N1, 0, 0, tw1);
+  } else {
+    fft_cols_m(f.N1, st, f, S, nb, 1, 0, 1, rows_valid, f.N1, 0, 0, tw1);
+  }
+}
+
+void fft_cols_inverse(hipStream_t st, const FftGeom &f, double2 *S, int nb, int rows_store, const double2 *tw1) {
+  if (f.B > 1) {
+    fft_cols_m(f.B, st, f, S, nb, f.A, f.B, 1, f.N1, f.N1, 1, 1, tw1);
+    fft_cols_m(f.A, st, f, S, nb, f.B, 1, f.B, f.N1, rows_store, 1, 0, tw1);
+  } else {
+    fft_cols_m(f.N1, st, f, S, nb, 1, 0, 1, f.N1, rows_store, 1, 0, tw1);
+  }
+}
+
+// The FP64 contraction corr(R64, D64) by FFT with the outputs of `o` in MODE
+// (as corr_mfma writes them).  The dictionary spectra are computed unless
+// ctx says the "fft_dhat" slot already holds those of D64.
+template <class Rz, int MODE>
+int corr_fft64(DeviceState *ds, hipStream_t stream, const Geom &g, const FftGeom &f, int kc, const double *R64,
+               const double *D64, const CorrOut &o, Fp64Ctx *ctx) {
+  const FftWs w = fft_ws(g, f, kc);
+  double2 *tw, *dhat, *E = nullptr, *rhat, *shat;
+  double *G;
+  WS("fft_tw", w.tw, tw);
+  WS("fft_dhat", w.dhat, dhat);
+  if (w.e) WS("fft_e", w.e, E);
+  WS("fft_rhat", w.rhat, rhat);
+  WS("fft_shat", w.shat, shat);
+  WS("fft_g", w.G, G);
+  double2 *tw1 = tw, *tw2 = tw + f.N1;
+  hipLaunchKernelGGL(fft_twiddles, dim3(blocks_for(f.N1, 256)), dim3(256), 0, stream, f.N1, tw1);
+  hipLaunchKernelGGL(fft_twiddles, dim3(blocks_for(f.N2, 256)), dim3(256), 0, stream, f.N2, tw2);
+  const size_t lds_row = sizeof(double2) * (size_t)f.M2;
+  const int KP = g.K * g.P;
+  if (!ctx || !ctx->dhat_ok || ctx->dhat != dhat) {
+    if (E) {
+      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(256), lds_row, stream, f, D64,
+                         (long long)g.L1 * g.L2, g.L2, g.L2, tw2, E, (long long)g.L1 * f.F2p);
+      if (f.B > 1)
+        fft_cols_m(f.B, stream, f, dhat, KP, f.A, f.B, 1, f.N1, f.N1, 0, 0, tw1, E, (long long)g.L1 * f.F2p, g.L1);
+      else
+        fft_cols_m(f.N1, stream, f, dhat, KP, 1, 0, 1, f.N1, f.N1, 0, 0, tw1, E, (long long)g.L1 * f.F2p, g.L1);
+    } else {
+      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(256), lds_row, stream, f, D64,
+                         (long long)g.L1 * g.L2, g.L2, g.L2, tw2, dhat, f.plane);
+      fft_cols_forward(stream, f, dhat, KP, g.L1, tw1);
+    }
+    if (ctx) {
+      ctx->dhat_ok = true;
+      ctx->dhat = dhat;
+    }
+  }
+  hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.T1, g.P), dim3(256), lds_row, stream, f, R64,
+                     (long long)g.T1 * g.T2, g.T2, g.T2, tw2, rhat, f.plane);
+  fft_cols_forward(stream, f, rhat, g.P, g.T1, tw1);
+  const long long HW = (long long)g.H * g.W;
+  const double scale = 1.0 / ((double)f.N1 * f.M2);
+  for (int k0 = 0; k0 < g.K; k0 += kc) {
+    const int nk = std::min(kc, g.K - k0);
+    hipLaunchKernelGGL(fft_product, dim3(grid_stride_blocks(f.plane)), dim3(256), 0, stream, f.plane, g.P, k0, nk,
+                       rhat, dhat, shat);
+    fft_cols_inverse(stream, f, shat, nk, g.H, tw1);
+    hipLaunchKernelGGL(fft_rows_c2r, dim3(g.H, nk), dim3(256), lds_row, stream, f, shat, f.plane, tw2,
+                       G + (long long)k0 * HW, HW, g.W, scale);
+  }
+  const unsigned nb = (unsigned)std::min<long long>((HW + 63) / 64, 16384);
+  hipLaunchKernelGGL((fft_epilogue<MODE, Rz>), dim3(nb), dim3(256), 0, stream, g, G, o);
+  HIPCK(hipGetLastError());
+  return DCDL_OK;
+}
+
 // ------------------------------------------------------------- DtD
 // Geometry of the DtD image (dtd_image) and whether the FP64 matrix cores
 // take its correlation.
@@ -345,13 +544,19 @@ int run_dtd(DeviceState *ds, hipStream_t stream, const Geom &g, const R *D, R *d
 }
 
 // The contraction actually used for a requested dcdl_corr_prec on data of
-// type R: AUTO picks BF16X3 for FP32 and F64 for FP64; the matrix-core
+// type R: AUTO picks BF16X3 for FP32 and F64 for FP64; F64_FFT stays where
+// allowed and its transform sizes apply, else becomes F64; the matrix-core
 // paths fall back to DIRECT when the staged windows would not fit.  -1 for a
 // BF16 request on FP64 data.
-int resolve_prec(int want, bool f32, const Geom &g) {
+int resolve_prec(int want, bool f32, const Geom &g, bool allow_fft = false) {
   int p = want == DCDL_CORR_AUTO ? (f32 ? DCDL_CORR_BF16X3 : DCDL_CORR_F64) : want;
-  if (p < DCDL_CORR_F64 || p > DCDL_CORR_DIRECT) return -1;
+  if (p < DCDL_CORR_F64 || p > DCDL_CORR_F64_FFT) return -1;
   if ((p == DCDL_CORR_BF16 || p == DCDL_CORR_BF16X3) && !f32) return -1;
+  if (p == DCDL_CORR_F64_FFT) {
+    FftGeom f;
+    if (allow_fft && fft_geom(g, &f)) return p;
+    p = DCDL_CORR_F64;
+  }
   if (p != DCDL_CORR_DIRECT && !mf_supported(g, mf_of(p))) p = DCDL_CORR_DIRECT;
   return p;
 }
@@ -378,12 +583,36 @@ int corr_beta_at(hipStream_t stream, const Geom &g, int prec, const R *Xin, cons
 // stored in `used`.
 template <class R>
 int beta_init(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, int want, R *beta,
-              CorrTimer *tm = nullptr, int *used = nullptr) {
-  const int prec = resolve_prec(want, std::is_same<R, float>::value, g);
+              CorrTimer *tm = nullptr, int *used = nullptr, Fp64Ctx *ctx = nullptr) {
+  int prec = resolve_prec(want, std::is_same<R, float>::value, g, true);
   if (prec < 0) return fail(DCDL_EINVAL, "beta_prec %d is not available for this dtype", want);
-  if (used) *used = prec;
   CorrOut ob{};
   ob.beta = beta;
+  if (prec == DCDL_CORR_F64_FFT) {
+    // FP64 by FFT (the data and atoms in FP64 in the "res64" and "D64" slots);
+    // the matrix cores if its workspace does not fit
+    FftGeom f;
+    int kc = 0;
+    if (fft64_pick(ds, g, 2, &f, &kc)) {
+      if (used) *used = prec;
+      const long long nx = (long long)g.P * g.T1 * g.T2, nd = (long long)g.K * g.P * g.L1 * g.L2;
+      double *X64, *D64;
+      WS("res64", sizeof(double) * nx, X64);
+      WS("D64", sizeof(double) * nd, D64);
+      hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, X64);
+      hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
+      Fp64Ctx local;
+      if (tm) {
+        int rc = tm->begin(stream);
+        if (rc) return rc;
+      }
+      int rc = corr_fft64<R, CORR_BETA>(ds, stream, g, f, kc, X64, D64, ob, ctx ? ctx : &local);
+      if (rc || !tm) return rc;
+      return tm->end(stream);
+    }
+    prec = mf_supported(g, MF_F64) ? DCDL_CORR_F64 : DCDL_CORR_DIRECT;
+  }
+  if (used) *used = prec;
   void *pk = nullptr;
   if (prec != DCDL_CORR_DIRECT) {
     const int mp = mf_of(prec);
@@ -426,6 +655,20 @@ int corr64(hipStream_t stream, const Geom &g, const double *R64, const double *D
   return run_corr<double, double, Rz, MODE>(stream, g, R64, D64, o);
 }
 
+// The FP64 contraction of one call: by FFT when ctx's method picks it for
+// this geometry, else corr64.
+template <class Rz, int MODE>
+int corr64x(DeviceState *ds, hipStream_t stream, const Geom &g, const double *R64, const double *D64,
+            const void *pk64, const CorrOut &o, Fp64Ctx *ctx) {
+  FftGeom f;
+  int kc = 0;
+  if (ctx && fft64_pick(ds, g, ctx->method, &f, &kc)) {
+    ++ctx->n_fft;
+    return corr_fft64<Rz, MODE>(ds, stream, g, f, kc, R64, D64, o, ctx);
+  }
+  return corr64<Rz, MODE>(stream, g, R64, D64, pk64, o);
+}
+
 // FP64 residual res = X - Z*D of a position-major z, enqueued without host
 // synchronisation; acc[0] += sum |z|, acc[1] += nnz (acc must start at 0).
 template <class R>
@@ -448,7 +691,7 @@ template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
             int positive, double *obj, double *kkt, long long *nnz, const R *beta_cmp = nullptr,
             const double *nrm64 = nullptr, double *drift = nullptr, R *beta_fix = nullptr,
-            CorrTimer *tm = nullptr, double *g64 = nullptr) {
+            CorrTimer *tm = nullptr, double *g64 = nullptr, Fp64Ctx *ctx = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -472,7 +715,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   void *pk64;
   if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
   if (tm && (rc = tm->begin(stream))) return rc;
-  rc = corr64<R, CORR_KKT>(stream, g, res, D64, pk64, o);
+  rc = corr64x<R, CORR_KKT>(ds, stream, g, res, D64, pk64, o, ctx);
   if (rc) return rc;
   if (tm && (rc = tm->end(stream))) return rc;
   double h[5];
@@ -490,7 +733,8 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
 // With fresh = false it reuses the residual and D64 left by check64.
 template <class R>
 int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
-                  const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr, double *g64 = nullptr) {
+                  const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr, double *g64 = nullptr,
+                  Fp64Ctx *ctx = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -511,7 +755,7 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   int rc = pack64<R>(ds, stream, g, D, &pk64);
   if (rc) return rc;
   if (tm && (rc = tm->begin(stream))) return rc;
-  rc = corr64<R, CORR_BETA>(stream, g, res, D64, pk64, ob);
+  rc = corr64x<R, CORR_BETA>(ds, stream, g, res, D64, pk64, ob, ctx);
   if (rc || !tm) return rc;
   return tm->end(stream);
 }
@@ -764,12 +1008,16 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   hipLaunchKernelGGL(norms64<R>, dim3(g.K), dim3(256), 0, stream, g.K, g.P * g.L1 * g.L2, D, nrm64);
   CorrTimer tm_init(evs.e[3], evs.e[4]), tm64(evs.e[5], evs.e[6]);
   int init_prec = DCDL_CORR_F64;
+  // the solve's FP64 contractions share one set of dictionary spectra when
+  // they run by FFT
+  Fp64Ctx f64;
+  f64.method = o->fp64_method;
   if (o->warm_start) {
     launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z_out, zpm);
-    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64))) return rc;
+    if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, nullptr, &f64))) return rc;
   } else {
     HIPCK(hipMemsetAsync(zpm, 0, sizeof(R) * nz, stream));
-    if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta, &tm_init, &init_prec))) return rc;
+    if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta, &tm_init, &init_prec, &f64))) return rc;
   }
   const R lam = (R)o->lambda, tol = (R)o->tol;
   launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
@@ -831,7 +1079,9 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   // K (2L1-1)(2L2-1) FP64 table entries each, cost under half the dense
   // contraction's 2 (16 ceil(K/16)) P L1 L2 flops per position (rates of the
   // two paths on gfx950: about 6 TB/s of table reads, 55 TFLOP/s of FP64 MFMA)
-  const double dense_s = 2.0 * 16 * ((g.K + 15) / 16) * g.P * g.L1 * g.L2 * (double)HW / 55e12;
+  FftGeom fgeom;
+  int fkc = 0;
+  const double dense_s = fft64_pick(ds, g, f64.method, &fgeom, &fkc) ? fft64_seconds(g, fgeom) : mfma64_seconds(g);
   const long long max_changes = std::max(1ll, std::min((long long)(0.5 * dense_s * 6e12 / (8.0 * g.K * g.U1 * g.U2)),
                                                        HW * g.K));
   CorrTimer tm_inc(evs.e[3], evs.e[4]);
@@ -911,7 +1161,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       // chunk, and the sweep certificate could never be reached.)
       ++n_refresh;
       if ((rc = want_ref())) return rc;
-      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, gref))) return rc;
+      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, gref, &f64))) return rc;
       if (gref) {
         HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
         have_ref = true;
@@ -938,7 +1188,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     if (!inc_used) {
       if ((rc = want_ref())) return rc;
       rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now,
-                      beta, &tm64, gref);
+                      beta, &tm64, gref, &f64);
       if (rc) return rc;
       have_ref = false;
     }
@@ -1002,6 +1252,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     info->t_check_inc_s = tm_inc.s;
     info->n_check_inc = tm_inc.n;
     info->n_changed = (int32_t)std::min<long long>(n_changed, INT32_MAX);
+    info->n_fft64 = f64.n_fft + (init_prec == DCDL_CORR_F64_FFT ? 1 : 0);
   }
   return status;
 }
@@ -1038,7 +1289,8 @@ int lambda_max_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
   void *pk64;
   int rc = pack64<double>(ds, stream, g, D64, &pk64);
   if (rc) return rc;
-  if ((rc = corr64<double, CORR_ABSMAX>(stream, g, X64, D64, pk64, o))) return rc;
+  Fp64Ctx ctx;
+  if ((rc = corr64x<double, CORR_ABSMAX>(ds, stream, g, X64, D64, pk64, o, &ctx))) return rc;
   HIPCK(hipMemcpyAsync(out, scal, sizeof(double), hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
   return DCDL_OK;
@@ -1252,7 +1504,7 @@ int dicodile_corr(const dcdl_shape *shape, dcdl_dtype dtype, const void *X, cons
   if (rc) return rc;
   if (!X || !D || !out) return fail(DCDL_EINVAL, "NULL pointer");
   if (dtype != DCDL_F32 && dtype != DCDL_F64) return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
-  if (prec < DCDL_CORR_AUTO || prec > DCDL_CORR_DIRECT) return fail(DCDL_EINVAL, "unknown precision %d", prec);
+  if (prec < DCDL_CORR_AUTO || prec > DCDL_CORR_F64_FFT) return fail(DCDL_EINVAL, "unknown precision %d", prec);
   if (dtype == DCDL_F64 && (prec == DCDL_CORR_BF16 || prec == DCDL_CORR_BF16X3))
     return fail(DCDL_EINVAL, "the BF16 contractions need FP32 data");
   PROLOGUE();
@@ -1274,14 +1526,16 @@ int dicodile_objective_kkt(const dcdl_shape *shape, dcdl_dtype dtype, const void
     float *zpm;
     WS("zpm_check", sizeof(float) * nz, zpm);
     launch_to_position_major<float, float>(stream, HW, g.K, g.KS, (const float *)z, zpm);
+    Fp64Ctx ctx;
     return check64<float>(ds, stream, g, (const float *)X, (const float *)D, zpm, lambda, positive, objective, kkt,
-                          nullptr);
+                          nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &ctx);
   } else if (dtype == DCDL_F64) {
     double *zpm;
     WS("zpm_check", sizeof(double) * nz, zpm);
     launch_to_position_major<double, double>(stream, HW, g.K, g.KS, (const double *)z, zpm);
+    Fp64Ctx ctx;
     return check64<double>(ds, stream, g, (const double *)X, (const double *)D, zpm, lambda, positive, objective,
-                           kkt, nullptr);
+                           kkt, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, &ctx);
   }
   return fail(DCDL_EINVAL, "unknown dtype %d", (int)dtype);
 }
