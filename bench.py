@@ -452,6 +452,28 @@ def run_serving(args):
     print(json.dumps(out), flush=True)
 
 
+def fft64_bytes(P, T, K, L, KS, s_beta):
+    """HBM bytes of one FP64 correlation by FFT, pass by pass, for an image
+    (P, T1, T2) and K atoms (L1, L2): transform sizes are the powers of two
+    covering T, spectra hold N1 x F2p complex values (F2p = N2/2 + 1 padded to
+    16).  Returned per epilogue mode, and the dictionary spectra (once per
+    solve)."""
+    T1, T2 = T
+    N1, N2 = 1 << (T1 - 1).bit_length(), 1 << (T2 - 1).bit_length()
+    M2 = N2 // 2
+    F2p = (M2 + 1 + 15) // 16 * 16
+    sp = 16.0 * N1 * F2p
+    H, W = T1 - L[0] + 1, T2 - L[1] + 1
+    HW = H * W
+    fwd = P * (8.0 * T1 * T2 + sp) + 2 * 2 * P * sp            # rows, two column passes
+    prod = (P + K * P) * sp + K * sp                              # products
+    inv = 2 * K * sp + K * sp + K * sp * H / N1 + K * (H * F2p * 16.0 + 8.0 * HW)  # B', A', rows
+    ep_g = 8.0 * K * HW                                           # G read
+    beta = fwd + prod + inv + ep_g + HW * KS * (s_beta + s_beta)  # + z read, beta written
+    kkt = fwd + prod + inv + ep_g + HW * KS * 3 * s_beta          # + z and kept beta read, beta written
+    return {"beta": beta, "kkt": kkt, "dict_spectra": K * P * sp}
+
+
 MFMA_PEAK_TFS = {"f64": 78.6, "bf16": 2500.0, "bf16x3": 2500.0 / 3, "direct": 157.3}
 
 
@@ -779,7 +801,7 @@ def run_solve(args):
                         "bytes_formula": "n_patched*K*3*s_beta + (visit_positions + n_checked)*s_move"},
     }
     fl = corr_flop(positions, K, P, taps)
-    init_prec = {0: "auto", 1: "f64", 2: "bf16", 3: "bf16x3", 4: "direct"}.get(infos[-1]["init_prec"], "?")
+    init_prec = {0: "auto", 1: "f64", 2: "bf16", 3: "bf16x3", 4: "direct", 5: "f64_fft"}.get(infos[-1]["init_prec"], "?")
     t_init = sum(i["t_init_corr_s"] for i in infos)
     if t_init > 0:
         peak = MFMA_PEAK_TFS.get(init_prec, 157.3)
@@ -790,7 +812,22 @@ def run_solve(args):
             "seconds": t_init / args.steps, "launches": 1, "flop_per_launch": fl}
     t64 = sum(i["t_corr64_s"] for i in infos)
     n64 = sum(i["n_corr64"] for i in infos)
-    if t64 > 0:
+    n_fft = sum(i["n_fft64"] for i in infos) - sum(1 for i in infos if i["init_prec"] == 5)
+    if t64 > 0 and n_fft > 0:
+        # FP64 contractions by FFT: HBM bytes of their passes as designed (the
+        # drift correction writes beta, the check reads the kept beta and
+        # rewrites it), plus the dictionary spectra once per solve
+        KS = K if f64 else (K + 3) // 4 * 4
+        fb = fft64_bytes(P, tuple(X.shape[1:]), K, L, KS, s_beta)
+        byt = (fb["beta"] + fb["kkt"] * (n64 / args.steps - 1) + fb["dict_spectra"]) * args.steps
+        kernels["corr_fft64"] = {
+            "bound": "hbm", "kernel": "FP64 correlation by FFT (fft_rows_r2c, fft_cols, fft_product, "
+                                      "fft_rows_c2r, fft_epilogue)",
+            "achieved": byt / t64 / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": byt / t64 / 1e9 / HBM_PEAK_GBS, "traffic": None, "seconds": t64 / args.steps,
+            "launches": n64 / args.steps, "bytes_per_launch": {k: v for k, v in fb.items()},
+            "bytes_formula": "passes of dcdl_fft.h: spectra 16 N1 F2p bytes each (see DESIGN.md)"}
+    elif t64 > 0:
         ach = fl * n64 / t64 / 1e12
         kernels["corr_mfma_f64"] = {
             "bound": "mfma", "kernel": "corr_mfma<f64> (drift correction and KKT check)", "achieved": ach,
@@ -864,21 +901,25 @@ def run_solve(args):
     if not args.no_variants:
         variants = {}
         if rgb:
-            for vp, fa in (("bf16x3", 0), ("bf16", 0)):
-                if vp == prec and fa == fix_after:
+            # other initialisations, and the configured one with its FP64
+            # contractions on the matrix cores instead of by FFT
+            for vp, fa, fm in (("bf16x3", 0, "auto"), ("bf16", 0, "auto"), ("f64_fft", 0, "auto"),
+                               (prec, fix_after, "mfma")):
+                if vp == prec and fa == fix_after and fm == "auto":
                     continue
-                vo = dict(opts, beta_prec=vp)
+                vo = dict(opts, beta_prec=vp, fp64_method=fm)
                 vo.pop("refresh_every", None)
                 vo.pop("refresh_limit", None)
                 if fa > 0:
                     vo.update(refresh_every=fa, refresh_limit=1)
                 _, iv = dl.dicodile_csc(X, D, lam, tol, z_out=z, **vo)
-                variants[f"init_{vp}_fix{fa}"] = {
+                variants[f"init_{vp}_fix{fa}" + ("_fp64_mfma" if fm == "mfma" else "")] = {
                     "status": iv["status"], "time_to_kkt_tol_ms": iv["t_total_s"] * 1e3,
                     "rounds": iv["n_rounds"], "passes": iv["n_passes"], "kkt": iv["kkt"],
                     "objective_rel_diff": (iv["objective"] - last["objective"]) / abs(last["objective"]),
                     "t_init_corr_ms": iv["t_init_corr_s"] * 1e3, "t_corr64_ms": iv["t_corr64_s"] * 1e3,
-                    "n_corr64": iv["n_corr64"], "beta_drift_at_first_check": iv["beta_drift"]}
+                    "n_corr64": iv["n_corr64"], "n_fft64": iv["n_fft64"],
+                    "beta_drift_at_first_check": iv["beta_drift"]}
         elif args.workload == "image_1024" and not args.grid:
             # the library's own worker grid beside the configured 16 x 16 one
             vo = dict(opts)

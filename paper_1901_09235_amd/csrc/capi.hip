@@ -1068,10 +1068,17 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   const int refresh = o->refresh_every > 0 ? o->refresh_every : 0;
   const int refresh_limit = o->refresh_limit > 0 ? o->refresh_limit : 0;
   int n_refresh = 0;
+  // The dense FP64 contraction: by FFT or on the matrix cores (fp64_method).
+  FftGeom fgeom;
+  int fkc = 0;
+  const bool dense_fft = fft64_pick(ds, g, f64.method, &fgeom, &fkc);
   // FP64 reference of the incremental check: g and z of the last dense FP64
-  // contraction (its residual stays in the "res64" slot).  Not used by the
-  // no-allocation entry point, whose scratch holds the dense path only.
-  const bool inc_ok = ds->arena == nullptr;
+  // contraction (its residual stays in the "res64" slot).  Used with the
+  // matrix-core contraction only: the FFT contraction costs less than
+  // carrying forward the changes of a solve's rounds (and keeping G would add
+  // its writes to every contraction).  Not used by the no-allocation entry
+  // point, whose scratch holds the dense path only.
+  const bool inc_ok = ds->arena == nullptr && !dense_fft;
   bool have_ref = false;
   double *gref = nullptr;
   R *zref = nullptr;
@@ -1079,9 +1086,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
   // K (2L1-1)(2L2-1) FP64 table entries each, cost under half the dense
   // contraction's 2 (16 ceil(K/16)) P L1 L2 flops per position (rates of the
   // two paths on gfx950: about 6 TB/s of table reads, 55 TFLOP/s of FP64 MFMA)
-  FftGeom fgeom;
-  int fkc = 0;
-  const double dense_s = fft64_pick(ds, g, f64.method, &fgeom, &fkc) ? fft64_seconds(g, fgeom) : mfma64_seconds(g);
+  const double dense_s = dense_fft ? fft64_seconds(g, fgeom) : mfma64_seconds(g);
   const long long max_changes = std::max(1ll, std::min((long long)(0.5 * dense_s * 6e12 / (8.0 * g.K * g.U1 * g.U2)),
                                                        HW * g.K));
   CorrTimer tm_inc(evs.e[3], evs.e[4]);

@@ -104,6 +104,29 @@ __device__ __forceinline__ void dft_r(double2 *v, bool inverse) {
   }
 }
 
+// The twiddles w^r, r < R, of a radix-R butterfly from w^1, w^2 and w^4 read
+// from the table (index m1 = the table index of w^1): at most two products
+// each, so their error stays within a few FP64 ulps.
+template <int R>
+__device__ __forceinline__ void stage_twiddles(double2 *w, const double2 *__restrict__ tw, long long m1, bool inverse) {
+  w[0] = make_double2(1.0, 0.0);
+  w[1] = tw[m1];
+  if constexpr (R >= 4) {
+    w[2] = tw[2 * m1];
+    w[3] = c_mul(w[1], w[2]);
+  }
+  if constexpr (R == 8) {
+    w[4] = tw[4 * m1];
+    w[5] = c_mul(w[1], w[4]);
+    w[6] = c_mul(w[2], w[4]);
+    w[7] = c_mul(w[3], w[4]);
+  }
+  if (inverse) {
+#pragma unroll
+    for (int r = 1; r < R; ++r) w[r].y = -w[r].y;
+  }
+}
+
 // One radix-R stage of the Stockham FFT (decimation in time, natural order
 // in and out) of n points in LDS buffer a, span Ns: butterfly j reads
 // a[j + r n / R], twiddles them by exp(-+2 pi i r (j mod Ns) / (Ns R)), takes
@@ -121,14 +144,12 @@ __device__ __forceinline__ void lds_stage(double2 *a, int n, int Ns, const doubl
     if (j < nb) {
       const int jm = j & (Ns - 1);
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double2 x = a[j + r * nb];
-        if (r > 0 && jm > 0) {
-          double2 w = tw[(long long)r * jm * (n / (Ns * R)) * tws];
-          if (inverse) w.y = -w.y;
-          x = c_mul(x, w);
-        }
-        v[q][r] = x;
+      for (int r = 0; r < R; ++r) v[q][r] = a[j + r * nb];
+      if (jm > 0) {
+        double2 w[R];
+        stage_twiddles<R>(w, tw, (long long)jm * (n / (Ns * R)) * tws, inverse);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], w[r]);
       }
       dft_r<R>(v[q], inverse);
     }
@@ -205,13 +226,21 @@ __global__ __launch_bounds__(256) void fft_rows_c2r(FftGeom f, const double2 *__
   extern __shared__ double2 fsm[];
   double2 *a = fsm;
   const double2 *X = S + blockIdx.y * sb + (long long)blockIdx.x * f.F2p;
-  for (int k = threadIdx.x; k < f.M2; k += blockDim.x) {
-    // Z[k] = E[k] + i O[k] with E = (X[k] + conj X[M2-k]) / 2 and
-    // O = conj(w^k) (X[k] - conj X[M2-k]) / 2, the transforms of the even
-    // and odd samples
-    const double2 xa = X[k], xb = c_conj(X[f.M2 - k]);
-    const double2 s = c_add(xa, xb), t = c_mul(c_conj(tw2[k]), c_sub(xa, xb));
-    a[k] = make_double2(0.5 * (s.x - t.y), 0.5 * (s.y + t.x));
+  // Z[k] = E[k] + i O[k] with E = (X[k] + conj X[M2-k]) / 2 and
+  // O = conj(w^k) (X[k] - conj X[M2-k]) / 2, the transforms of the even and
+  // odd samples; one thread forms Z[k] and Z[M2-k] from the same two reads
+  for (int k = threadIdx.x; k <= f.M2 / 2; k += blockDim.x) {
+    const double2 xk = X[k], xm = X[f.M2 - k];
+    {
+      const double2 xb = c_conj(xm);
+      const double2 s = c_add(xk, xb), t = c_mul(c_conj(tw2[k]), c_sub(xk, xb));
+      a[k] = make_double2(0.5 * (s.x - t.y), 0.5 * (s.y + t.x));
+    }
+    if (k > 0 && k < f.M2 - k) {
+      const double2 xb = c_conj(xk);
+      const double2 s = c_add(xm, xb), t = c_mul(c_conj(tw2[f.M2 - k]), c_sub(xm, xb));
+      a[f.M2 - k] = make_double2(0.5 * (s.x - t.y), 0.5 * (s.y + t.x));
+    }
   }
   __syncthreads();
   lds_fft(a, f.M2, tw2, 2, true);
@@ -285,18 +314,16 @@ __device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int i = j + r * (M / R);
-      double2 x;
-      if constexpr (FIRST) {
-        x = col_load(ca, g0 + gs, i, c0 + c);
-      } else {
-        x = buf[(gs * M + i) * 16 + c];
-        if (r > 0 && jm > 0) {
-          double2 w = ca.tw1[(long long)r * jm * (M / (Ns * R)) * tws];
-          if (ca.inverse) w.y = -w.y;
-          x = c_mul(x, w);
-        }
-      }
-      v[q][r] = x;
+      if constexpr (FIRST)
+        v[q][r] = col_load(ca, g0 + gs, i, c0 + c);
+      else
+        v[q][r] = buf[(gs * M + i) * 16 + c];
+    }
+    if (!FIRST && jm > 0) {
+      double2 w[R];
+      stage_twiddles<R>(w, ca.tw1, (long long)jm * (M / (Ns * R)) * tws, ca.inverse);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q][r] = c_mul(v[q][r], w[r]);
     }
     dft_r<R>(v[q], ca.inverse);
   }

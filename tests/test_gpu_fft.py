@@ -103,6 +103,8 @@ def test_solve_with_fp64_method_matches_oracle(lib, method):
                                beta_prec="bf16", refresh_every=2, refresh_limit=1, fp64_method=method)
     assert info["converged"] == 1
     assert (info["n_fft64"] > 0) == (method == "fft")
+    # the incremental check follows the matrix-core contraction only
+    assert info["n_check_inc"] == 0 or method == "mfma"
     zo, _ = oracle.lgcd(X64, D64, lam, 1e-9 * lam)
     f_opt = oracle.objective(X64, D64, zo, lam)
     f = oracle.objective(X64, D64, z.double().cpu().numpy(), lam)

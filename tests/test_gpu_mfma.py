@@ -172,9 +172,10 @@ def test_single_drift_correction_after_bf16_start(lib):
     Dd = D.astype(np.float32).astype(np.float64)
     lam = 0.1 * oracle.lambda_max(X, Dd)
     z, info = lib.dicodile_csc(dev(X, torch.float32), dev(Dd, torch.float32), lam, 1e-5 * lam,
-                               beta_prec="bf16", refresh_every=2, refresh_limit=1, grid=(3, 3), timeout_s=60)
+                               beta_prec="bf16", refresh_every=2, refresh_limit=1, grid=(3, 3), timeout_s=60,
+                               fp64_method="mfma")
     assert info["status"] == "OK", info
-    assert info["init_prec"] == 2 and info["t_init_corr_s"] > 0
+    assert info["init_prec"] == 2 and info["t_init_corr_s"] > 0 and info["n_fft64"] == 0
     # the one correction (a dense FP64 contraction), then one check per pass
     # after it, each carried forward from the correction's FP64 gradient
     assert info["n_corr64"] == 1 and info["n_check_inc"] == info["n_passes"] - 1, info
@@ -213,10 +214,12 @@ def test_failed_check_rebuilds_beta_in_the_same_contraction(lib):
 
 @pytest.mark.parametrize("positive", [False, True])
 def test_incremental_check_equals_the_dense_check(lib, positive):
-    """After the one drift correction, the final check carries that FP64
-    contraction's gradient and residual forward over the coordinates changed
-    since (info n_check_inc); its objective and strict KKT equal a dense FP64
-    check of the returned z (dicodile_objective_kkt) and the oracle's."""
+    """After the one drift correction (on the matrix cores: the incremental
+    check follows the matrix-core contraction only), the final check carries
+    that FP64 contraction's gradient and residual forward over the
+    coordinates changed since (info n_check_inc); its objective and strict
+    KKT equal a dense FP64 check of the returned z (dicodile_objective_kkt)
+    and the oracle's."""
     D = synth.gaussian_dictionary(np.random.Generator(np.random.PCG64(14)), 7, 2, (9, 7))
     pb = synth.make_problem("p", 906, P=2, T=(90, 77), K=7, L=(9, 7), rho=0.004, amp="exp", sigma=0.05, D=D)
     X = pb.X.astype(np.float32).astype(np.float64)
@@ -224,7 +227,7 @@ def test_incremental_check_equals_the_dense_check(lib, positive):
     lam = 0.1 * oracle.lambda_max(X, Dd, positive=positive)
     Xt, Dt = dev(X, torch.float32), dev(Dd, torch.float32)
     z, info = lib.dicodile_csc(Xt, Dt, lam, 1e-5 * lam, positive=positive, beta_prec="bf16", refresh_every=2,
-                               refresh_limit=1, grid=(3, 3), timeout_s=60)
+                               refresh_limit=1, grid=(3, 3), timeout_s=60, fp64_method="mfma")
     assert info["status"] == "OK", info
     assert info["n_check_inc"] >= 1 and info["t_check_inc_s"] > 0, info
     assert info["n_corr64"] == 1, info  # the drift correction only
