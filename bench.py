@@ -466,8 +466,8 @@ def fft64_bytes(P, T, K, L, KS, s_beta):
     H, W = T1 - L[0] + 1, T2 - L[1] + 1
     HW = H * W
     fwd = P * (8.0 * T1 * T2 + sp) + 2 * 2 * P * sp            # rows, two column passes
-    prod = (P + K * P) * sp + K * sp                              # products
-    inv = 2 * K * sp + K * sp + K * sp * H / N1 + K * (H * F2p * 16.0 + 8.0 * HW)  # B', A', rows
+    prod = (P + K * P) * sp + K * sp                              # products fused with the first inverse pass
+    inv = K * sp + K * sp * H / N1 + K * (H * F2p * 16.0 + 8.0 * HW)  # second inverse pass, rows
     ep_g = 8.0 * K * HW                                           # G read
     beta = fwd + prod + inv + ep_g + HW * KS * (s_beta + s_beta)  # + z read, beta written
     kkt = fwd + prod + inv + ep_g + HW * KS * 3 * s_beta          # + z and kept beta read, beta written

@@ -15,7 +15,8 @@ OUT_DIR = os.path.join(HERE, "_build")
 LIB_NAME = "libdicodile_mi355x.so"
 LIB_PATH = os.path.join(OUT_DIR, LIB_NAME)
 SOURCES = ["capi.hip"]
-HEADERS = ["dcdl_device.h", "dcdl_kernels.h", "dcdl_mfma.h", "mfma_host.inc", "batch.inc", "tune.inc", "dict.inc", "serve.inc", "dcdl_dict.h"]
+HEADERS = ["dcdl_device.h", "dcdl_kernels.h", "dcdl_mfma.h", "dcdl_check.h", "dcdl_fft.h", "mfma_host.inc", "batch.inc",
+           "tune.inc", "dict.inc", "serve.inc", "dcdl_dict.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -450,14 +450,14 @@ int corr_fft64(DeviceState *ds, hipStream_t stream, const Geom &g, const FftGeom
   const int KP = g.K * g.P;
   if (!ctx || !ctx->dhat_ok || ctx->dhat != dhat) {
     if (E) {
-      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(256), lds_row, stream, f, D64,
+      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(kRowThreads), lds_row, stream, f, D64,
                          (long long)g.L1 * g.L2, g.L2, g.L2, tw2, E, (long long)g.L1 * f.F2p);
       if (f.B > 1)
         fft_cols_m(f.B, stream, f, dhat, KP, f.A, f.B, 1, f.N1, f.N1, 0, 0, tw1, E, (long long)g.L1 * f.F2p, g.L1);
       else
         fft_cols_m(f.N1, stream, f, dhat, KP, 1, 0, 1, f.N1, f.N1, 0, 0, tw1, E, (long long)g.L1 * f.F2p, g.L1);
     } else {
-      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(256), lds_row, stream, f, D64,
+      hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.L1, KP), dim3(kRowThreads), lds_row, stream, f, D64,
                          (long long)g.L1 * g.L2, g.L2, g.L2, tw2, dhat, f.plane);
       fft_cols_forward(stream, f, dhat, KP, g.L1, tw1);
     }
@@ -466,17 +466,44 @@ int corr_fft64(DeviceState *ds, hipStream_t stream, const Geom &g, const FftGeom
       ctx->dhat = dhat;
     }
   }
-  hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.T1, g.P), dim3(256), lds_row, stream, f, R64,
+  hipLaunchKernelGGL(fft_rows_r2c<double>, dim3(g.T1, g.P), dim3(kRowThreads), lds_row, stream, f, R64,
                      (long long)g.T1 * g.T2, g.T2, g.T2, tw2, rhat, f.plane);
   fft_cols_forward(stream, f, rhat, g.P, g.T1, tw1);
   const long long HW = (long long)g.H * g.W;
   const double scale = 1.0 / ((double)f.N1 * f.M2);
   for (int k0 = 0; k0 < g.K; k0 += kc) {
     const int nk = std::min(kc, g.K - k0);
-    hipLaunchKernelGGL(fft_product, dim3(grid_stride_blocks(f.plane)), dim3(256), 0, stream, f.plane, g.P, k0, nk,
-                       rhat, dhat, shat);
-    fft_cols_inverse(stream, f, shat, nk, g.H, tw1);
-    hipLaunchKernelGGL(fft_rows_c2r, dim3(g.H, nk), dim3(256), lds_row, stream, f, shat, f.plane, tw2,
+    if (g.P <= 4) {
+      // products fused into the first inverse column pass
+      const int M = f.B > 1 ? f.B : f.N1;
+      const ColArgs ca = f.B > 1 ? ColArgs{f, shat, f.A, f.B, 1, f.N1, f.N1, 1, 1, tw1, nullptr, 0, 0}
+                                 : ColArgs{f, shat, 1, 0, 1, f.N1, g.H, 1, 0, tw1, nullptr, 0, 0};
+      const dim3 grid(f.F2p / 16, (ca.ngroups + 128 / M - 1) / (128 / M)), blk(256);
+#define DCDL_COLS_PRODUCT(MM, PP) \
+  hipLaunchKernelGGL((fft_cols_product<MM, PP>), grid, blk, 0, stream, ca, rhat, dhat, k0, nk)
+      if (M == 64) {
+        switch (g.P) {
+          case 1: DCDL_COLS_PRODUCT(64, 1); break;
+          case 2: DCDL_COLS_PRODUCT(64, 2); break;
+          case 3: DCDL_COLS_PRODUCT(64, 3); break;
+          default: DCDL_COLS_PRODUCT(64, 4); break;
+        }
+      } else {
+        switch (g.P) {
+          case 1: DCDL_COLS_PRODUCT(128, 1); break;
+          case 2: DCDL_COLS_PRODUCT(128, 2); break;
+          case 3: DCDL_COLS_PRODUCT(128, 3); break;
+          default: DCDL_COLS_PRODUCT(128, 4); break;
+        }
+      }
+#undef DCDL_COLS_PRODUCT
+      if (f.B > 1) fft_cols_m(f.A, stream, f, shat, nk, f.B, 1, f.B, f.N1, g.H, 1, 0, tw1);
+    } else {
+      hipLaunchKernelGGL(fft_product, dim3(grid_stride_blocks(f.plane)), dim3(256), 0, stream, f.plane, g.P, k0,
+                         nk, rhat, dhat, shat);
+      fft_cols_inverse(stream, f, shat, nk, g.H, tw1);
+    }
+    hipLaunchKernelGGL(fft_rows_c2r, dim3(g.H, nk), dim3(kRowThreads), lds_row, stream, f, shat, f.plane, tw2,
                        G + (long long)k0 * HW, HW, g.W, scale);
   }
   const unsigned nb = (unsigned)std::min<long long>((HW + 63) / 64, 16384);

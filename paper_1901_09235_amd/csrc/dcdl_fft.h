@@ -66,6 +66,9 @@ __global__ __launch_bounds__(256) void fft_twiddles(int N, double2 *__restrict__
   tw[m] = make_double2(c, s);
 }
 
+// Threads of the row-transform workgroups.
+constexpr int kRowThreads = 512;
+
 // R-point DFT (R = 2, 4, 8) of v in place, natural order; the inverse uses
 // the conjugate roots (unnormalised).
 template <int R>
@@ -131,15 +134,17 @@ __device__ __forceinline__ void stage_twiddles(double2 *w, const double2 *__rest
 // in and out) of n points in LDS buffer a, span Ns: butterfly j reads
 // a[j + r n / R], twiddles them by exp(-+2 pi i r (j mod Ns) / (Ns R)), takes
 // the R-point DFT and writes a[(j / Ns) Ns R + (j mod Ns) + r Ns].  In place:
-// every read precedes a barrier before the writes.  At most 512 butterflies
-// (two per thread of 256).  tw[m tws] = exp(-2 pi i m / n).
+// every read precedes a barrier before the writes.  At most 512 butterflies,
+// one per thread of the 512-thread row workgroups.  tw[m tws] =
+// exp(-2 pi i m / n).
 template <int R>
 __device__ __forceinline__ void lds_stage(double2 *a, int n, int Ns, const double2 *__restrict__ tw, int tws,
                                           bool inverse) {
+  constexpr int Q = 512 / kRowThreads;
   const int nb = n / R;
-  double2 v[2][R];
+  double2 v[Q][R];
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int j = threadIdx.x + q * blockDim.x;
     if (j < nb) {
       const int jm = j & (Ns - 1);
@@ -156,7 +161,7 @@ __device__ __forceinline__ void lds_stage(double2 *a, int n, int Ns, const doubl
   }
   __syncthreads();
 #pragma unroll
-  for (int q = 0; q < 2; ++q) {
+  for (int q = 0; q < Q; ++q) {
     const int j = threadIdx.x + q * blockDim.x;
     if (j < nb) {
       const int idx = (j / Ns) * Ns * R + (j & (Ns - 1));
@@ -169,7 +174,7 @@ __device__ __forceinline__ void lds_stage(double2 *a, int n, int Ns, const doubl
 
 // Stockham FFT of n <= 4096 points (a power of two) in LDS buffer a, natural
 // order in and out, in radix-8 stages (a last radix-4 or -2 stage when log2 n
-// is not a multiple of 3).  Every thread of the 256 takes part.
+// is not a multiple of 3).  Every thread of the kRowThreads takes part.
 __device__ void lds_fft(double2 *a, int n, const double2 *__restrict__ tw, int tws, bool inverse) {
   for (int Ns = 1; Ns < n;) {
     const int rem = n / Ns;
@@ -190,7 +195,7 @@ __device__ void lds_fft(double2 *a, int n, const double2 *__restrict__ tw, int t
 // spectrum X[0 .. M2] of the real row x (zero beyond `cols`), written with
 // zero padding up to F2p.  LDS: M2 complex values.
 template <class Rin>
-__global__ __launch_bounds__(256) void fft_rows_r2c(FftGeom f, const Rin *__restrict__ x, long long xb, int xp,
+__global__ __launch_bounds__(kRowThreads) void fft_rows_r2c(FftGeom f, const Rin *__restrict__ x, long long xb, int xp,
                                                     int cols, const double2 *__restrict__ tw2,
                                                     double2 *__restrict__ out, long long ob) {
   extern __shared__ double2 fsm[];
@@ -220,7 +225,7 @@ __global__ __launch_bounds__(256) void fft_rows_r2c(FftGeom f, const Rin *__rest
 // One output row h < H per workgroup (blockIdx.x), one spectrum per
 // blockIdx.y: the real row whose half spectrum is row h of S, times `scale`,
 // written for columns < W into G (row pitch W, batch stride gb).
-__global__ __launch_bounds__(256) void fft_rows_c2r(FftGeom f, const double2 *__restrict__ S, long long sb,
+__global__ __launch_bounds__(kRowThreads) void fft_rows_c2r(FftGeom f, const double2 *__restrict__ S, long long sb,
                                                     const double2 *__restrict__ tw2, double *__restrict__ G,
                                                     long long gb, int W, double scale) {
   extern __shared__ double2 fsm[];
@@ -282,7 +287,7 @@ __device__ __forceinline__ double2 col_load(const ColArgs &ca, int g, int i, int
   return v;
 }
 
-__device__ __forceinline__ void col_store(const ColArgs &ca, int g, int i, int col, double2 v) {
+__device__ __forceinline__ void col_store(const ColArgs &ca, long long plane, int g, int i, int col, double2 v) {
   if (g >= ca.ngroups) return;
   const int row = g * ca.gmul + i * ca.stride;
   if (row >= ca.rows_store) return;
@@ -291,15 +296,22 @@ __device__ __forceinline__ void col_store(const ColArgs &ca, int g, int i, int c
     if (ca.inverse) w.y = -w.y;
     v = c_mul(v, w);
   }
-  ca.S[blockIdx.z * ca.f.plane + (long long)row * ca.f.F2p + col] = v;
+  ca.S[plane * ca.f.plane + (long long)row * ca.f.F2p + col] = v;
 }
+
+// The plain input of a column pass: spectrum blockIdx.z of S (or E).
+struct ColLoadPlain {
+  __device__ __forceinline__ double2 operator()(const ColArgs &ca, int, int g, int i, int col) const {
+    return col_load(ca, g, i, col);
+  }
+};
 
 // Radix-R stage of span Ns of the M-point Stockham FFTs of a workgroup's 16 x
 // (128 / M) sequences (element i of sequence (gs, c) at buf[(gs M + i) 16 + c]
 // between stages): the first stage loads from the spectra, the last stores to
 // them, so M <= 8 never touches LDS and M = 64 crosses it once.
-template <int M, int Ns>
-__device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
+template <int M, int Ns, class Load>
+__device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf, const Load &load, long long out_plane) {
   constexpr int R = (M / Ns) % 8 == 0 ? 8 : ((M / Ns) % 4 == 0 ? 4 : 2);
   constexpr int Q = 2048 / R / 256;  // butterflies per thread
   constexpr bool FIRST = Ns == 1, LAST = Ns * R == M;
@@ -315,7 +327,7 @@ __device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
     for (int r = 0; r < R; ++r) {
       const int i = j + r * (M / R);
       if constexpr (FIRST)
-        v[q][r] = col_load(ca, g0 + gs, i, c0 + c);
+        v[q][r] = load(ca, q * R + r, g0 + gs, i, c0 + c);
       else
         v[q][r] = buf[(gs * M + i) * 16 + c];
     }
@@ -338,7 +350,7 @@ __device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
       for (int r = 0; r < R; ++r) buf[(gs * M + idx + r * Ns) * 16 + c] = v[q][r];
     }
     __syncthreads();
-    col_stages<M, Ns * R>(ca, buf);
+    col_stages<M, Ns * R>(ca, buf, load, out_plane);
   } else {
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -346,7 +358,7 @@ __device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
       const int c = b & 15, rest = b >> 4, gs = rest / (M / R), j = rest % (M / R);
       const int idx = (j / Ns) * Ns * R + (j & (Ns - 1));
 #pragma unroll
-      for (int r = 0; r < R; ++r) col_store(ca, g0 + gs, idx + r * Ns, c0 + c, v[q][r]);
+      for (int r = 0; r < R; ++r) col_store(ca, out_plane, g0 + gs, idx + r * Ns, c0 + c, v[q][r]);
     }
   }
 }
@@ -354,7 +366,56 @@ __device__ __forceinline__ void col_stages(const ColArgs &ca, double2 *buf) {
 template <int M>
 __global__ __launch_bounds__(256) void fft_cols(ColArgs ca) {
   __shared__ double2 buf[M > 8 ? 2048 : 1];
-  col_stages<M, 1>(ca, buf);
+  col_stages<M, 1>(ca, buf, ColLoadPlain(), blockIdx.z);
+}
+
+// The first inverse column pass fused with the spectral product: the input
+// of spectrum kk is sum_p Rhat_p conj(Dhat_(k0+kk),p) at each element, for
+// kk < nk in turn, with the workgroup's Rhat values (P <= 4 channels, the
+// eight first-stage elements of each thread) held in registers across the
+// atoms.
+// Dhat is stored [k][p]; the outputs go to planes kk of ca.S.
+template <int P>
+struct ColLoadProduct {
+  const double2 (*rr)[8];
+  const double2 *dk;  // Dhat of atom k, channel 0
+  __device__ __forceinline__ double2 operator()(const ColArgs &ca, int e8, int g, int i, int col) const {
+    if (g >= ca.ngroups) return make_double2(0.0, 0.0);
+    const long long e = (long long)(g * ca.gmul + i * ca.stride) * ca.f.F2p + col;
+    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int p = 0; p < P; ++p) acc = c_add(acc, c_mulc(rr[p][e8], dk[p * ca.f.plane + e]));
+    return acc;
+  }
+};
+
+template <int M, int P>
+__global__ __launch_bounds__(256) void fft_cols_product(ColArgs ca, const double2 *__restrict__ Rh,
+                                                        const double2 *__restrict__ Dh, int k0, int nk) {
+  __shared__ double2 buf[M > 8 ? 2048 : 1];
+  constexpr int R0 = M % 8 == 0 ? 8 : (M % 4 == 0 ? 4 : 2), Q0 = 2048 / R0 / 256;
+  static_assert(Q0 * R0 == 8, "eight first-stage elements per thread");
+  constexpr int GPW = 128 / M;
+  const int c0 = blockIdx.x * 16, g0 = blockIdx.y * GPW;
+  double2 rr[P][8];
+#pragma unroll
+  for (int q = 0; q < Q0; ++q) {
+    const int b = threadIdx.x + 256 * q;
+    const int c = b & 15, rest = b >> 4, gs = rest / (M / R0), j = rest % (M / R0);
+    const int g = g0 + gs;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int i = j + r * (M / R0);
+      const long long e = (long long)(g * ca.gmul + i * ca.stride) * ca.f.F2p + c0 + c;
+#pragma unroll
+      for (int p = 0; p < P; ++p) rr[p][q * R0 + r] = g < ca.ngroups ? Rh[p * ca.f.plane + e] : make_double2(0.0, 0.0);
+    }
+  }
+  for (int kk = 0; kk < nk; ++kk) {
+    __syncthreads();  // the previous atom's last reads of buf are done
+    const ColLoadProduct<P> load{rr, Dh + (long long)(k0 + kk) * P * ca.f.plane};
+    col_stages<M, 1>(ca, buf, load, kk);
+  }
 }
 
 // Shat_kk = sum_p Rhat_p conj(Dhat_(k0+kk),p) for kk < nk at every element of
