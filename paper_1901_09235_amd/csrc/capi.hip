@@ -703,7 +703,7 @@ int residual64_async(hipStream_t stream, const Geom &g, const R *X, const double
                      double *acc) {
   const long long nx = (long long)g.P * g.T1 * g.T2, HW = (long long)g.H * g.W;
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, res);
-  const unsigned nb = (unsigned)std::min<long long>((HW + 3) / 4, 65536);
+  const unsigned nb = (unsigned)std::min<long long>((HW + 31) / 32, 16384);
   hipLaunchKernelGGL((residual_dense<R, double>), dim3(nb), dim3(256), 0, stream, g, zpm, D64, res, acc);
   HIPCK(hipGetLastError());
   return DCDL_OK;
@@ -1618,8 +1618,10 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
   HIPCK(hipMemsetAsync(cnt, 0, sizeof(unsigned int) * 2 * g.K, stream));
   HIPCK(hipMemsetAsync(phi64, 0, sizeof(double) * nphi, stream));
   HIPCK(hipMemsetAsync(psi64, 0, sizeof(double) * npsi, stream));
-  const unsigned gx = (unsigned)std::min<long long>(blocks_for(HW, 256), 1024);
-  hipLaunchKernelGGL(count_per_atom<R>, dim3(gx, g.K), dim3(256), 0, stream, (int)HW, g.K, z, cnt);
+  HIPCK(hipMemsetAsync(nzc, 0, sizeof(int) * HW, stream));
+  // z position-major with the non-zero counts of every position and atom
+  hipLaunchKernelGGL(to_position_major_counts<R>, dim3((unsigned)((HW + 63) / 64), (unsigned)((g.KS + 63) / 64)),
+                     dim3(256), 0, stream, (int)HW, g.K, g.KS, z, zpm, nzc, cnt);
   std::vector<unsigned int> hc(g.K);
   HIPCK(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned int) * g.K, hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
@@ -1646,10 +1648,8 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
     WS("st_chunks", sizeof(Chunk) * chunks.size(), d_chunks);
     HIPCK(hipMemcpyAsync(cnt + g.K, off.data(), sizeof(unsigned int) * g.K, hipMemcpyHostToDevice, stream));
     HIPCK(hipMemcpyAsync(d_chunks, chunks.data(), sizeof(Chunk) * chunks.size(), hipMemcpyHostToDevice, stream));
-    hipLaunchKernelGGL(list_per_atom<R>, dim3(gx, g.K), dim3(256), 0, stream, (int)HW, g.K, z, cnt + g.K, list);
-    const unsigned pb = blocks_for(HW, 256);
-    launch_to_position_major<R, R>(stream, HW, g.K, g.KS, z, zpm);
-    hipLaunchKernelGGL(count_per_position<R>, dim3(pb), dim3(256), 0, stream, (int)HW, g.K, g.KS, zpm, nzc);
+    hipLaunchKernelGGL(list_from_position_major<R>, dim3(grid_stride_blocks(HW)), dim3(256), 0, stream, (int)HW,
+                       g.K, g.KS, zpm, nzc, cnt + g.K, list);
     hipLaunchKernelGGL(psi_kernel<R>, dim3((unsigned)chunks.size()), dim3(256), 0, stream, g, d_chunks, list, X,
                        psi64);
     const long long nb = total < 65536 ? total : 65536;

@@ -377,36 +377,47 @@ __global__ __launch_bounds__(256) void sum_squares(long long n, const double *__
 
 // res -= Z*D for a position-major z (atom stride KS), one wave per position:
 // the lanes find the non-zero atoms of the position, then scatter each one's
-// shifted atom (eq. model) with FP64 atomics.  Also accumulates sum |z| and
-// the non-zero count into acc[0], acc[1] (doubles).  No host round trip.
+// shifted atom (eq. model) with FP64 atomics.  A wave loads the atom rows of
+// RP positions at once (RP independent loads in flight) before it scans them.
+// Also accumulates sum |z| and the non-zero count into acc[0], acc[1]
+// (doubles).  No host round trip.
 template <class R, class Rd>
 __global__ __launch_bounds__(256) void residual_dense(Geom g, const R *__restrict__ z, const Rd *__restrict__ D,
                                                       double *__restrict__ res, double *__restrict__ acc) {
+  constexpr int RP = 8;
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63;
   const long long HW = (long long)g.H * g.W;
   const int PL = g.P * g.L1 * g.L2, LL = g.L1 * g.L2;
   const long long plane = (long long)g.T1 * g.T2;
   double l1 = 0.0, cnt = 0.0;
-  for (long long pos = (long long)blockIdx.x * 4 + (threadIdx.x >> 6); pos < HW; pos += (long long)gridDim.x * 4) {
-    const int h = (int)(pos / g.W), w = (int)(pos - (pos / g.W) * g.W);
+  const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = (long long)gridDim.x * 4;
+  for (long long pos0 = wave * RP; pos0 < HW; pos0 += nwaves * RP) {
     for (int kb = 0; kb < g.K; kb += 64) {
       const int k = kb + lane;
-      const R v = k < g.K ? z[pos * g.KS + k] : R(0);
-      unsigned long long m = __ballot(v != R(0));
-      if (v != R(0)) {
-        l1 += fabs((double)v);
-        cnt += 1.0;
-      }
-      while (m) {
-        const int src = __ffsll((long long)m) - 1;
-        m &= m - 1;
-        const double zv = (double)__shfl(v, src, 64);
-        const Rd *dk = D + (long long)(kb + src) * PL;
-        for (int i = lane; i < PL; i += 64) {
-          const int p = i / LL, r = i - p * LL;
-          const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
-          atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -zv * (double)dk[i]);
+      R v[RP];
+#pragma unroll
+      for (int q = 0; q < RP; ++q) v[q] = (k < g.K && pos0 + q < HW) ? z[(pos0 + q) * g.KS + k] : R(0);
+#pragma unroll
+      for (int q = 0; q < RP; ++q) {
+        unsigned long long m = __ballot(v[q] != R(0));
+        if (!m) continue;
+        if (v[q] != R(0)) {
+          l1 += fabs((double)v[q]);
+          cnt += 1.0;
+        }
+        const long long pos = pos0 + q;
+        const int h = (int)(pos / g.W), w = (int)(pos - (pos / g.W) * g.W);
+        while (m) {
+          const int src = __ffsll((long long)m) - 1;
+          m &= m - 1;
+          const double zv = (double)__shfl(v[q], src, 64);
+          const Rd *dk = D + (long long)(kb + src) * PL;
+          for (int i = lane; i < PL; i += 64) {
+            const int p = i / LL, r = i - p * LL;
+            const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
+            atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -zv * (double)dk[i]);
+          }
         }
       }
     }
@@ -484,43 +495,66 @@ __global__ __launch_bounds__(256) void phi_kernel(Geom g, const NzEntry *__restr
   }
 }
 
-// Non-zero atoms per position of a position-major z.
+
+// to_position_major for the dictionary statistics: also counts the non-zeros
+// of every position into nzc and of every atom into cnt (both zeroed by the
+// caller) from the transposed tile.
 template <class R>
-__global__ __launch_bounds__(256) void count_per_position(int HW, int K, int KS, const R *__restrict__ zpm,
-                                                          int *__restrict__ nzc) {
-  const int pos = blockIdx.x * blockDim.x + threadIdx.x;
-  if (pos >= HW) return;
-  int c = 0;
-  for (int k = 0; k < K; ++k) c += zpm[(long long)pos * KS + k] != R(0);
-  nzc[pos] = c;
+__global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, int KS, const R *__restrict__ src,
+                                                                R *__restrict__ dst, int *__restrict__ nzc,
+                                                                unsigned int *__restrict__ cnt) {
+  __shared__ R tile[64][65];
+  const long long p0 = (long long)blockIdx.x * 64;
+  const int k0 = blockIdx.y * 64;
+  const int pn = (int)min(64ll, HW - p0), kn = min(64, KS - k0);
+  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
+    const int kk = i >> 6, pp = i & 63;
+    if (kk < kn && pp < pn) {
+      const int k = k0 + kk;
+      tile[kk][pp] = k < K ? src[(long long)k * HW + p0 + pp] : R(0);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < pn * kn; i += 256) {
+    const int pp = i / kn, kk = i - pp * kn;
+    dst[(p0 + pp) * KS + k0 + kk] = tile[kk][pp];
+  }
+  const int ka = min(kn, K - k0);  // real atoms of the tile
+  if (threadIdx.x < 64) {
+    const int pp = threadIdx.x;
+    int c = 0;
+    if (pp < pn)
+      for (int kk = 0; kk < ka; ++kk) c += tile[kk][pp] != R(0);
+    if (c) atomicAdd(&nzc[p0 + pp], c);
+  } else if (threadIdx.x < 128) {
+    const int kk = threadIdx.x - 64;
+    unsigned int c = 0;
+    if (kk < ka)
+      for (int pp = 0; pp < pn; ++pp) c += tile[kk][pp] != R(0);
+    if (c) atomicAdd(&cnt[k0 + kk], c);
+  }
 }
 
-// Per-atom counts of the non-zeros of an atom-major z (K, HW).
+// Lists the non-zeros of a position-major z grouped by atom (cursor[k] starts
+// at the atom's offset in the list), reading z only at positions whose
+// non-zero count is positive.
 template <class R>
-__global__ __launch_bounds__(256) void count_per_atom(int HW, int K, const R *__restrict__ z, unsigned int *__restrict__ cnt) {
-  const int k = blockIdx.y;
-  unsigned int c = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += gridDim.x * blockDim.x)
-    c += z[(long long)k * HW + i] != R(0);
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-  if ((threadIdx.x & 63) == 0 && c) atomicAdd(&cnt[k], c);
-}
-
-// Lists the non-zeros of an atom-major z grouped by atom: cursor[k] starts at
-// the atom's offset in the list.
-template <class R>
-__global__ __launch_bounds__(256) void list_per_atom(int HW, int K, const R *__restrict__ z,
-                                                     unsigned int *__restrict__ cursor, NzEntry *__restrict__ list) {
-  const int k = blockIdx.y;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < HW; i += gridDim.x * blockDim.x) {
-    const R v = z[(long long)k * HW + i];
-    if (v != R(0)) {
-      const unsigned int slot = atomicAdd(&cursor[k], 1u);
-      NzEntry e;
-      e.pos = i;
-      e.k = k;
-      e.z = (double)v;
-      list[slot] = e;
+__global__ __launch_bounds__(256) void list_from_position_major(int HW, int K, int KS, const R *__restrict__ zpm,
+                                                                const int *__restrict__ nzc,
+                                                                unsigned int *__restrict__ cursor,
+                                                                NzEntry *__restrict__ list) {
+  for (int pos = blockIdx.x * blockDim.x + threadIdx.x; pos < HW; pos += gridDim.x * blockDim.x) {
+    if (nzc[pos] == 0) continue;
+    for (int k = 0; k < K; ++k) {
+      const R v = zpm[(long long)pos * KS + k];
+      if (v != R(0)) {
+        const unsigned int slot = atomicAdd(&cursor[k], 1u);
+        NzEntry e;
+        e.pos = pos;
+        e.k = k;
+        e.z = (double)v;
+        list[slot] = e;
+      }
     }
   }
 }
