@@ -62,6 +62,8 @@ int main(void) {
   printf("%zu %zu %zu %zu\\n", offsetof(dcdl_csc_opts, refresh_limit), offsetof(dcdl_csc_info, t_init_corr_s),
          offsetof(dcdl_csc_info, n_corr64), offsetof(dcdl_csc_info, n_changed));
   printf("%zu %zu\\n", offsetof(dcdl_csc_opts, audit), offsetof(dcdl_csc_opts, audit_rounds));
+  printf("%zu %zu %d\\n", offsetof(dcdl_csc_opts, fp64_method), offsetof(dcdl_csc_info, n_fft64),
+         (int)DCDL_CORR_F64_FFT);
   return 0;
 }
 """)
@@ -91,6 +93,8 @@ int main(void) {
                     dl.CscInfo.n_changed.offset]
     aud = [int(v) for v in lines[8].split()]
     assert aud == [dl.CscOpts.audit.offset, dl.CscOpts.audit_rounds.offset]
+    fft = [int(v) for v in lines[9].split()]
+    assert fft == [dl.CscOpts.fp64_method.offset, dl.CscInfo.n_fft64.offset, dl.CORR_PREC["f64_fft"]]
 
 
 def test_argument_checks_before_device_access(lib):
