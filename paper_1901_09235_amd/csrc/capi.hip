@@ -1615,13 +1615,17 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
   WS("st_psi", sizeof(double) * npsi, psi64);
   WS("st_zpm", sizeof(R) * nz, zpm);
   WS("st_nzc", sizeof(int) * HW, nzc);
+  uint32_t *nzbits;
+  const long long nbw = (HW + 63) / 64 * 2;
+  WS("st_nzbits", sizeof(uint32_t) * nbw, nzbits);
   HIPCK(hipMemsetAsync(cnt, 0, sizeof(unsigned int) * 2 * g.K, stream));
   HIPCK(hipMemsetAsync(phi64, 0, sizeof(double) * nphi, stream));
   HIPCK(hipMemsetAsync(psi64, 0, sizeof(double) * npsi, stream));
   HIPCK(hipMemsetAsync(nzc, 0, sizeof(int) * HW, stream));
+  HIPCK(hipMemsetAsync(nzbits, 0, sizeof(uint32_t) * nbw, stream));
   // z position-major with the non-zero counts of every position and atom
   hipLaunchKernelGGL(to_position_major_counts<R>, dim3((unsigned)((HW + 63) / 64), (unsigned)((g.KS + 63) / 64)),
-                     dim3(256), 0, stream, (int)HW, g.K, g.KS, z, zpm, nzc, cnt);
+                     dim3(256), 0, stream, (int)HW, g.K, g.KS, z, zpm, nzc, cnt, nzbits);
   std::vector<unsigned int> hc(g.K);
   HIPCK(hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned int) * g.K, hipMemcpyDeviceToHost, stream));
   HIPCK(hipStreamSynchronize(stream));
@@ -1653,7 +1657,7 @@ int dict_stats_impl(DeviceState *ds, hipStream_t stream, const Geom &g, const R 
     hipLaunchKernelGGL(psi_kernel<R>, dim3((unsigned)chunks.size()), dim3(256), 0, stream, g, d_chunks, list, X,
                        psi64);
     const long long nb = total < 65536 ? total : 65536;
-    hipLaunchKernelGGL(phi_kernel<R>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, total, zpm, nzc, phi64);
+    hipLaunchKernelGGL(phi_kernel<R>, dim3((unsigned)nb), dim3(256), 0, stream, g, list, total, zpm, nzbits, phi64);
     HIPCK(hipGetLastError());
   }
   if (ztz)

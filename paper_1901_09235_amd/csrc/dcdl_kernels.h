@@ -471,38 +471,55 @@ __global__ __launch_bounds__(256) void psi_kernel(Geom g, const Chunk *__restric
 }
 
 // phi[k][k'][tau + L - 1] += z_k[w] z_k'[w + tau] for every listed non-zero
-// (k, w), scanning its window w + Phi in a position-major copy of z.
+// (k, w).  Its window w + Phi is scanned row by row in the bitmap of
+// non-empty positions (bit pos of nzbits: at most three words per window
+// row), and only the atoms of the set positions are read from the
+// position-major copy of z.
 template <class R>
 __global__ __launch_bounds__(256) void phi_kernel(Geom g, const NzEntry *__restrict__ list, long long nnz,
-                                                  const R *__restrict__ zpm, const int *__restrict__ nzc,
+                                                  const R *__restrict__ zpm, const uint32_t *__restrict__ nzbits,
                                                   double *__restrict__ phi) {
   const int nU = g.U1 * g.U2;
+  const int nwr = (g.U2 + 31) / 32 + 1;  // words one window row spans at most
   for (long long e = blockIdx.x; e < nnz; e += gridDim.x) {
     const NzEntry nz = list[e];
     const int h = nz.pos / g.W, w = nz.pos - (nz.pos / g.W) * g.W;
-    for (int u = threadIdx.x; u < nU; u += blockDim.x) {
-      const int u1 = u / g.U2, u2 = u - (u / g.U2) * g.U2;
-      const int hh = h + u1 - (g.L1 - 1), ww = w + u2 - (g.L2 - 1);
-      if (hh < 0 || hh >= g.H || ww < 0 || ww >= g.W) continue;
-      const int pos2 = hh * g.W + ww;
-      if (nzc[pos2] == 0) continue;
-      const R *zr = zpm + (long long)pos2 * g.KS;
-      for (int k2 = 0; k2 < g.K; ++k2) {
-        const R v = zr[k2];
-        if (v != R(0)) atomic_add_f64(phi + ((long long)nz.k * g.K + k2) * nU + u, nz.z * (double)v);
+    const int wlo = max(0, w - (g.L2 - 1)), whi = min(g.W, w + g.L2);  // window columns [wlo, whi)
+    for (int it = threadIdx.x; it < g.U1 * nwr; it += blockDim.x) {
+      const int u1 = it / nwr, wi = it - u1 * nwr;
+      const int hh = h + u1 - (g.L1 - 1);
+      if (hh < 0 || hh >= g.H) continue;
+      const long long row = (long long)hh * g.W;
+      const long long b0 = row + wlo, b1 = row + whi;  // bits [b0, b1)
+      const long long lo = ((b0 >> 5) + wi) << 5;       // first bit of this thread's word
+      if (lo >= b1) continue;
+      uint32_t m = nzbits[lo >> 5];
+      if (b0 > lo) m &= ~0u << (int)(b0 - lo);
+      if (b1 < lo + 32) m &= (1u << (int)(b1 - lo)) - 1u;
+      while (m) {
+        const int bit = __ffs(m) - 1;
+        m &= m - 1;
+        const long long pos2 = lo + bit;
+        const int u = u1 * g.U2 + (int)(pos2 - row) - w + (g.L2 - 1);
+        const R *zr = zpm + pos2 * g.KS;
+        for (int k2 = 0; k2 < g.K; ++k2) {
+          const R v = zr[k2];
+          if (v != R(0)) atomic_add_f64(phi + ((long long)nz.k * g.K + k2) * nU + u, nz.z * (double)v);
+        }
       }
     }
   }
 }
 
-
 // to_position_major for the dictionary statistics: also counts the non-zeros
-// of every position into nzc and of every atom into cnt (both zeroed by the
-// caller) from the transposed tile.
+// of every position into nzc and of every atom into cnt, and sets the bit of
+// every non-empty position in nzbits (all zeroed by the caller), from the
+// transposed tile.
 template <class R>
 __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, int KS, const R *__restrict__ src,
                                                                 R *__restrict__ dst, int *__restrict__ nzc,
-                                                                unsigned int *__restrict__ cnt) {
+                                                                unsigned int *__restrict__ cnt,
+                                                                uint32_t *__restrict__ nzbits) {
   __shared__ R tile[64][65];
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
@@ -526,6 +543,12 @@ __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, i
     if (pp < pn)
       for (int kk = 0; kk < ka; ++kk) c += tile[kk][pp] != R(0);
     if (c) atomicAdd(&nzc[p0 + pp], c);
+    // the tile's 64 positions are two whole words of the bitmap (p0 is a multiple of 64)
+    const unsigned long long bits = __ballot(c != 0);
+    if (pp == 0 && bits) {
+      atomicOr(&nzbits[p0 >> 5], (uint32_t)bits);
+      if (bits >> 32) atomicOr(&nzbits[(p0 >> 5) + 1], (uint32_t)(bits >> 32));
+    }
   } else if (threadIdx.x < 128) {
     const int kk = threadIdx.x - 64;
     unsigned int c = 0;
