@@ -1047,7 +1047,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     if ((rc = beta_init<R>(ds, stream, g, X, D, o->beta_prec, beta, &tm_init, &init_prec, &f64))) return rc;
   }
   const R lam = (R)o->lambda, tol = (R)o->tol;
-  launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
+  launch_init_moves<R>(stream, HW, g.K, g.KS, beta, o->warm_start ? zpm : nullptr, inv_n, lam, tol, o->positive,
+                       o->certify, score, meta);
   HIPCK(hipGetLastError());
   HIPCK(hipEventRecord(ev1, stream));
   HIPCK(hipEventSynchronize(ev1));

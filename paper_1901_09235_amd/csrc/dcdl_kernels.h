@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
 // the position's count of non-zero coordinates.  A position's 16-byte atom
 // groups are read by a segment of S lanes (S the power of two covering them,
 // at most a wave), so a wave reads contiguous memory, and the segment reduces
-// with shuffles.
+// with shuffles.  z = NULL stands for z = 0 (a cold start), which is not read.
 template <class R>
 __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R *__restrict__ beta,
                                                   const R *__restrict__ z, const R *__restrict__ inv_n, R lambda,
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R
     if (pos < HW)
       for (int q = sl; q < G; q += S) {
         const V b = *reinterpret_cast<const V *>(beta + pos * KS + q * VE);
-        const V zv = *reinterpret_cast<const V *>(z + pos * KS + q * VE);
+        const V zv = z ? *reinterpret_cast<const V *>(z + pos * KS + q * VE) : Vec<R>::zero();
 #pragma unroll
         for (int e = 0; e < VE; ++e) {
           const int k = q * VE + e;
