@@ -117,7 +117,9 @@ typedef struct {
   dcdl_dtype dtype;       /* precision of X, D, z_out and of the incremental beta/Z */
   int32_t no_soft_lock;   /* 1: disable the soft-lock test of eq. soft_lock (ablation of
                              Sec. 5 only; pair it with div_guard) */
-  int32_t threads;        /* threads per worker workgroup: 64, 128, 192, 256, 512 or 1024; 0 -> 256 */
+  int32_t threads;        /* threads per worker workgroup: 64, 128, 192, 256, 512 or 1024; 0 -> 256,
+                             or for images 1024 (512) when the worker grid fits the device with one
+                             (two) workgroups per CU */
   int32_t tile[2];        /* sub-domain size C_m per dimension; 0 -> 2 L_i (Sec. 3) */
   int32_t grid[2];        /* worker grid W_1 x W_2; 0 -> chosen by the library: ceil(extent / tile)
                              workers per axis, each at least L long, scaled down to the
