@@ -506,7 +506,7 @@ int corr_fft64(DeviceState *ds, hipStream_t stream, const Geom &g, const FftGeom
     hipLaunchKernelGGL(fft_rows_c2r, dim3(g.H, nk), dim3(kRowThreads), lds_row, stream, f, shat, f.plane, tw2,
                        G + (long long)k0 * HW, HW, g.W, scale);
   }
-  const unsigned nb = (unsigned)std::min<long long>((HW + 63) / 64, 16384);
+  const unsigned nb = (unsigned)std::min<long long>((HW + 63) / 64, 4096);
   hipLaunchKernelGGL((fft_epilogue<MODE, Rz>), dim3(nb), dim3(256), 0, stream, g, G, o);
   HIPCK(hipGetLastError());
   return DCDL_OK;
