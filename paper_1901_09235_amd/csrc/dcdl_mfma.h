@@ -138,13 +138,77 @@ __device__ __forceinline__ void mf_load_b(const typename MfT<PREC>::In *p, typen
   }
 }
 
+// BF16 window staging, one (row, column) cell per thread and step: the PC
+// channels of the chunk are read (coalesced along the row for each channel)
+// and written to LDS as one PC-element store.  Eight cells' loads are issued
+// before the first is converted, so a thread has 8 PC reads in flight; the
+// cell index advances by 256 without a division per element.  Copy 1
+// (NCOPY = 2) holds v - bf16(v).
+template <int NCOPY, int PC, class Rin>
+__device__ __forceinline__ void mf_stage_cells(const Geom &g, const Rin *__restrict__ X, int pc, int hbase, int w0,
+                                               int nrows, int TCX, int copy_elems, __bf16 *xs) {
+  constexpr int NB = 8;
+  const long long plane = (long long)g.T1 * g.T2;
+  const int tid = threadIdx.x, cells = nrows * TCX;
+  const int rstep = 256 / TCX, cstep = 256 - rstep * TCX;
+  int r = tid / TCX, c = tid - r * TCX;
+  for (int e0 = tid; e0 < cells; e0 += 256 * NB) {
+    float v[NB][PC];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int hh = hbase + r, ww = w0 + c;
+      const bool in = e0 + 256 * b < cells && hh < g.T1 && ww < g.T2;
+      const Rin *src = X + (long long)hh * g.T2 + ww;
+#pragma unroll
+      for (int pp = 0; pp < PC; ++pp) {
+        const int p = pc * PC + pp;
+        v[b][pp] = in && p < g.P ? (float)src[p * plane] : 0.0f;
+      }
+      r += rstep;
+      c += cstep;
+      if (c >= TCX) {
+        c -= TCX;
+        ++r;
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int e = e0 + 256 * b;
+      if (e >= cells) break;
+      __bf16 hi[PC], lo[PC];
+#pragma unroll
+      for (int pp = 0; pp < PC; ++pp) {
+        hi[pp] = (__bf16)v[b][pp];
+        lo[pp] = (__bf16)(v[b][pp] - (float)hi[pp]);
+      }
+      __bf16 *dst = xs + (long long)e * PC;
+#pragma unroll
+      for (int cp = 0; cp < NCOPY; ++cp) {
+        const __bf16 *hs = cp == 0 ? hi : lo;
+        __bf16 *d = dst + cp * copy_elems;
+        if constexpr (PC == 8)
+          *reinterpret_cast<uint4 *>(d) = *reinterpret_cast<const uint4 *>(hs);
+        else if constexpr (PC == 4)
+          *reinterpret_cast<uint2 *>(d) = *reinterpret_cast<const uint2 *>(hs);
+        else if constexpr (PC == 2)
+          *reinterpret_cast<uint32_t *>(d) = *reinterpret_cast<const uint32_t *>(hs);
+        else
+          d[0] = hs[0];
+      }
+    }
+  }
+}
+
 // TR x (4 NTW 16 / TR) positions per workgroup: TR = 1 for signals (the four
 // waves side by side along the row), TR = 4 for images (one row per wave).
 // PC = 0 takes the channel chunk from the plan (FP64, one element per lane).
 // TALL: the window of every t1 is staged once per channel chunk, TR + L1 - 1
 // rows (row wr + t1 serves wave wr at tap row t1), instead of TR rows per t1;
 // the steps of consecutive t1 then run without a barrier between them.
-template <int PREC, int MODE, int TR, int NTW, int MT, int PC, bool TALL, class Rin, class Rz>
+// SPSC > 0 fixes the steps per stage at compile time: the step loop unrolls
+// and window fragments that two (column tile, step) pairs share (the tile
+// 16 columns to the right, 16 / (KK / PC) steps earlier) are read once.
+template <int PREC, int MODE, int TR, int NTW, int MT, int PC, bool TALL, class Rin, class Rz, int SPSC = 0>
 __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *__restrict__ X,
                                                  const typename MfT<PREC>::In *__restrict__ Dpk, long long npk,
                                                  int m0, CorrOut o) {
@@ -183,6 +247,9 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
         __syncthreads();
         // stage rows h0 + (TALL ? 0 : t1) + r, columns w0 + c, channels pc PC + pp
         const int hbase = h0 + (TALL ? 0 : t1);
+        if constexpr (PREC != MF_F64 && PC > 0) {
+          mf_stage_cells<T::NCOPY, PC>(g, X, pc, hbase, w0, nrows, TCX, copy_elems, xs);
+        } else
         for (int e = tid; e < copy_elems; e += 256) {
           const int c = e % TCX, rest = e / TCX;
           const int pp = rest % pcs, r = rest / pcs;
@@ -202,17 +269,19 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
       }
       const long long sbase = ((long long)(t1 * pl.NPC + pc) * pl.SPS) * pl.MTT;
       const In *xrow = xs + (wr + (TALL ? t1 : 0)) * row_elems;
-      for (int s = 0; s < pl.SPS; ++s) {
+      const In *arow = Dpk + ((sbase + m0) * 64 + lane) * VPL;  // step 0, tile m0 of this stage
+      const long long astep = (long long)pl.MTT * 64 * VPL;
+      auto step = [&](int s) {
         In a[T::NCOPY][MT][VPL];
 #pragma unroll
         for (int m = 0; m < MT; ++m) {
-          const long long ai = ((sbase + (long long)s * pl.MTT + m0 + m) * 64 + lane) * VPL;
+          const In *ap = arow + s * astep + m * 64 * VPL;
 #pragma unroll
           for (int cp = 0; cp < T::NCOPY; ++cp) {
             if constexpr (VPL == 1)
-              a[cp][m][0] = Dpk[cp * npk + ai];
+              a[cp][m][0] = ap[cp * npk];
             else
-              *reinterpret_cast<uint4 *>(a[cp][m]) = *reinterpret_cast<const uint4 *>(Dpk + cp * npk + ai);
+              *reinterpret_cast<uint4 *>(a[cp][m]) = *reinterpret_cast<const uint4 *>(ap + cp * npk);
           }
         }
         const int rl = s * T::KK + (lane >> 4) * VPL;  // first reduction index of this lane
@@ -235,6 +304,12 @@ __global__ __launch_bounds__(256) void corr_mfma(Geom g, MfPlan pl, const Rin *_
             }
           }
         }
+      };
+      if constexpr (SPSC > 0) {
+#pragma unroll
+        for (int s = 0; s < SPSC; ++s) step(s);
+      } else {
+        for (int s = 0; s < pl.SPS; ++s) step(s);
       }
     }
 
