@@ -700,11 +700,11 @@ int corr64x(DeviceState *ds, hipStream_t stream, const Geom &g, const double *R6
 // synchronisation; acc[0] += sum |z|, acc[1] += nnz (acc must start at 0).
 template <class R>
 int residual64_async(hipStream_t stream, const Geom &g, const R *X, const double *D64, const R *zpm, double *res,
-                     double *acc) {
+                     double *acc, const uint32_t *meta = nullptr) {
   const long long nx = (long long)g.P * g.T1 * g.T2, HW = (long long)g.H * g.W;
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, X, res);
   const unsigned nb = (unsigned)std::min<long long>((HW + 31) / 32, 16384);
-  hipLaunchKernelGGL((residual_dense<R, double>), dim3(nb), dim3(256), 0, stream, g, zpm, D64, res, acc);
+  hipLaunchKernelGGL((residual_dense<R, double>), dim3(nb), dim3(256), 0, stream, g, zpm, D64, res, acc, meta);
   HIPCK(hipGetLastError());
   return DCDL_OK;
 }
@@ -718,7 +718,7 @@ template <class R>
 int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm, double lambda,
             int positive, double *obj, double *kkt, long long *nnz, const R *beta_cmp = nullptr,
             const double *nrm64 = nullptr, double *drift = nullptr, R *beta_fix = nullptr,
-            CorrTimer *tm = nullptr, double *g64 = nullptr, Fp64Ctx *ctx = nullptr) {
+            CorrTimer *tm = nullptr, double *g64 = nullptr, Fp64Ctx *ctx = nullptr, const uint32_t *meta = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -726,7 +726,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   WS("scal", 64, scal);
   hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
   HIPCK(hipMemsetAsync(scal, 0, 40, stream));
-  int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2);
+  int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2, meta);
   if (rc) return rc;
   hipLaunchKernelGGL(sum_squares, dim3(grid_stride_blocks(nx)), dim3(256), 0, stream, nx, res, scal);
   CorrOut o{};
@@ -739,6 +739,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
   o.result2 = scal + 4;
   o.beta = beta_fix;
   o.g64 = g64;
+  o.meta = meta;
   void *pk64;
   if ((rc = pack64<R>(ds, stream, g, D, &pk64))) return rc;
   if (tm && (rc = tm->begin(stream))) return rc;
@@ -761,7 +762,7 @@ int check64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, cons
 template <class R>
 int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X, const R *D, const R *zpm,
                   const double *nrm64, R *beta, bool fresh, CorrTimer *tm = nullptr, double *g64 = nullptr,
-                  Fp64Ctx *ctx = nullptr) {
+                  Fp64Ctx *ctx = nullptr, const uint32_t *meta = nullptr) {
   const long long nd = (long long)g.K * g.P * g.L1 * g.L2, nx = (long long)g.P * g.T1 * g.T2;
   double *D64, *res, *scal;
   WS("D64", sizeof(double) * nd, D64);
@@ -770,7 +771,7 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
     WS("scal", 64, scal);
     hipLaunchKernelGGL((convert_kernel<R, double>), dim3(grid_stride_blocks(nd)), dim3(256), 0, stream, nd, D, D64);
     HIPCK(hipMemsetAsync(scal, 0, 32, stream));
-    int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2);
+    int rc = residual64_async<R>(stream, g, X, D64, zpm, res, scal + 2, meta);
     if (rc) return rc;
   }
   CorrOut ob{};
@@ -778,6 +779,7 @@ int beta_from_z64(DeviceState *ds, hipStream_t stream, const Geom &g, const R *X
   ob.zpm = zpm;
   ob.nrm = nrm64;
   ob.g64 = g64;
+  ob.meta = meta;
   void *pk64;
   int rc = pack64<R>(ds, stream, g, D, &pk64);
   if (rc) return rc;
@@ -1208,7 +1210,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       // chunk, and the sweep certificate could never be reached.)
       ++n_refresh;
       if ((rc = want_ref())) return rc;
-      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, gref, &f64))) return rc;
+      if ((rc = beta_from_z64<R>(ds, stream, g, X, D, zpm, nrm64, beta, true, &tm64, gref, &f64, meta))) return rc;
       if (gref) {
         HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
         have_ref = true;
@@ -1235,7 +1237,7 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     if (!inc_used) {
       if ((rc = want_ref())) return rc;
       rc = check64<R>(ds, stream, g, X, D, zpm, o->lambda, o->positive, &obj, &kkt, &nnz, beta, nrm64, &drift_now,
-                      beta, &tm64, gref, &f64);
+                      beta, &tm64, gref, &f64, meta);
       if (rc) return rc;
       have_ref = false;
     }

@@ -467,12 +467,13 @@ __global__ __launch_bounds__(256) void fft_epilogue(Geom g, const double *__rest
         if (pos >= HW || k >= KW) continue;
         const double gv = t[kk][pp];
         if (MODE != CORR_ABSMAX && o.g64 && k < g.K) o.g64[pos * g.KS + k] = gv;
+        const bool zread = !o.meta || (o.meta[pos] >> 16) != 0;  // z is 0 at positions without non-zeros
         if (MODE == CORR_BETA) {
           double bv = gv;
-          if (o.zpm && k < g.K) bv += o.nrm[k] * (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+          if (o.zpm && k < g.K && zread) bv += o.nrm[k] * (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
           reinterpret_cast<Rz *>(o.beta)[pos * g.KS + k] = k < g.K ? (Rz)bv : Rz(0);
         } else if (MODE == CORR_KKT) {
-          const double z = (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k];
+          const double z = zread ? (double)reinterpret_cast<const Rz *>(o.zpm)[pos * g.KS + k] : 0.0;
           double vv;
           if (z == 0.0)
             vv = o.positive ? fmax(gv - o.lambda, 0.0) : fmax(fabs(gv) - o.lambda, 0.0);

@@ -149,6 +149,8 @@ struct CorrOut {
   const void *beta_cmp;  // CORR_KKT, optional: a maintained beta (H, W, KS) in Rz compared with
   double *result2;       //   G + n z (needs nrm); result2 receives the max absolute difference
   double *g64;           // CORR_KKT and CORR_BETA, optional: G in FP64, (H, W, KS), atoms < K only
+  const uint32_t *meta;  // optional, one word per position whose high 16 bits count the non-zeros
+                         // of zpm there: the FFT epilogue reads z only where that count is not 0
 };
 
 template <class Rin, class Racc, class Rz, int MODE, int KC, int TH>
@@ -379,46 +381,70 @@ __global__ __launch_bounds__(256) void sum_squares(long long n, const double *__
 // the lanes find the non-zero atoms of the position, then scatter each one's
 // shifted atom (eq. model) with FP64 atomics.  A wave loads the atom rows of
 // RP positions at once (RP independent loads in flight) before it scans them.
-// Also accumulates sum |z| and the non-zero count into acc[0], acc[1]
-// (doubles).  No host round trip.
+// With `meta` (one word per position, the high 16 bits counting the non-zeros
+// of z there) a wave instead reads the words of 64 positions in one load and
+// visits only the positions whose count is not 0: z itself is read where it
+// has non-zeros.  Also accumulates sum |z| and the non-zero count into acc[0],
+// acc[1] (doubles).  No host round trip.
+template <class R, class Rd>
+__device__ __forceinline__ void residual_scatter(const Geom &g, long long pos, int kb, R v, const Rd *__restrict__ D,
+                                                 double *__restrict__ res, double &l1, double &cnt) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long m = __ballot(v != R(0));
+  if (!m) return;
+  if (v != R(0)) {
+    l1 += fabs((double)v);
+    cnt += 1.0;
+  }
+  const int PL = g.P * g.L1 * g.L2, LL = g.L1 * g.L2;
+  const long long plane = (long long)g.T1 * g.T2;
+  const int h = (int)(pos / g.W), w = (int)(pos - (pos / g.W) * g.W);
+  while (m) {
+    const int src = __ffsll((long long)m) - 1;
+    m &= m - 1;
+    const double zv = (double)__shfl(v, src, 64);
+    const Rd *dk = D + (long long)(kb + src) * PL;
+    for (int i = lane; i < PL; i += 64) {
+      const int p = i / LL, r = i - p * LL;
+      const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
+      atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -zv * (double)dk[i]);
+    }
+  }
+}
+
 template <class R, class Rd>
 __global__ __launch_bounds__(256) void residual_dense(Geom g, const R *__restrict__ z, const Rd *__restrict__ D,
-                                                      double *__restrict__ res, double *__restrict__ acc) {
+                                                      double *__restrict__ res, double *__restrict__ acc,
+                                                      const uint32_t *__restrict__ meta) {
   constexpr int RP = 8;
   __shared__ double sh[4];
   const int lane = threadIdx.x & 63;
   const long long HW = (long long)g.H * g.W;
-  const int PL = g.P * g.L1 * g.L2, LL = g.L1 * g.L2;
-  const long long plane = (long long)g.T1 * g.T2;
   double l1 = 0.0, cnt = 0.0;
   const long long wave = (long long)blockIdx.x * 4 + (threadIdx.x >> 6), nwaves = (long long)gridDim.x * 4;
-  for (long long pos0 = wave * RP; pos0 < HW; pos0 += nwaves * RP) {
-    for (int kb = 0; kb < g.K; kb += 64) {
-      const int k = kb + lane;
-      R v[RP];
-#pragma unroll
-      for (int q = 0; q < RP; ++q) v[q] = (k < g.K && pos0 + q < HW) ? z[(pos0 + q) * g.KS + k] : R(0);
-#pragma unroll
-      for (int q = 0; q < RP; ++q) {
-        unsigned long long m = __ballot(v[q] != R(0));
-        if (!m) continue;
-        if (v[q] != R(0)) {
-          l1 += fabs((double)v[q]);
-          cnt += 1.0;
+  if (meta) {
+    for (long long c0 = wave * 64; c0 < HW; c0 += nwaves * 64) {
+      const long long mine = c0 + lane;
+      unsigned long long pm = __ballot(mine < HW && (meta[mine] >> 16) != 0);
+      while (pm) {
+        const long long pos = c0 + (__ffsll((long long)pm) - 1);
+        pm &= pm - 1;
+        for (int kb = 0; kb < g.K; kb += 64) {
+          const int k = kb + lane;
+          const R v = k < g.K ? z[pos * g.KS + k] : R(0);
+          residual_scatter<R, Rd>(g, pos, kb, v, D, res, l1, cnt);
         }
-        const long long pos = pos0 + q;
-        const int h = (int)(pos / g.W), w = (int)(pos - (pos / g.W) * g.W);
-        while (m) {
-          const int src = __ffsll((long long)m) - 1;
-          m &= m - 1;
-          const double zv = (double)__shfl(v[q], src, 64);
-          const Rd *dk = D + (long long)(kb + src) * PL;
-          for (int i = lane; i < PL; i += 64) {
-            const int p = i / LL, r = i - p * LL;
-            const int t1 = r / g.L2, t2 = r - (r / g.L2) * g.L2;
-            atomic_add_f64(res + p * plane + (long long)(h + t1) * g.T2 + (w + t2), -zv * (double)dk[i]);
-          }
-        }
+      }
+    }
+  } else {
+    for (long long pos0 = wave * RP; pos0 < HW; pos0 += nwaves * RP) {
+      for (int kb = 0; kb < g.K; kb += 64) {
+        const int k = kb + lane;
+        R v[RP];
+#pragma unroll
+        for (int q = 0; q < RP; ++q) v[q] = (k < g.K && pos0 + q < HW) ? z[(pos0 + q) * g.KS + k] : R(0);
+#pragma unroll
+        for (int q = 0; q < RP; ++q) residual_scatter<R, Rd>(g, pos0 + q, kb, v[q], D, res, l1, cnt);
       }
     }
   }
