@@ -1262,7 +1262,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
     HIPCK(hipStreamSynchronize(stream));
     t_check += now_s() - tc0;
   }
-  launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out);
+  // the per-position non-zero counts match z unless a launch ended on a neighbour wait
+  launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out, status == DCDL_ETIMEOUT ? nullptr : meta);
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
   if (info) {

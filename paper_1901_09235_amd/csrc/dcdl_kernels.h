@@ -325,16 +325,18 @@ __global__ __launch_bounds__(256) void to_position_major(int HW, int K, int KS, 
   }
 }
 
+// With `meta` (one word per position, the high 16 bits counting its
+// non-zeros) the rows of positions without non-zeros are not read: they are 0.
 template <class Rs, class Rd>
 __global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, const Rs *__restrict__ src,
-                                                     Rd *__restrict__ dst) {
+                                                     Rd *__restrict__ dst, const uint32_t *__restrict__ meta) {
   __shared__ Rd tile[64][65];
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int pn = (int)min(64ll, HW - p0), kn = min(64, K - k0);
   for (int i = threadIdx.x; i < pn * kn; i += 256) {
     const int pp = i / kn, kk = i - pp * kn;
-    tile[kk][pp] = (Rd)src[(p0 + pp) * KS + k0 + kk];
+    tile[kk][pp] = meta && (meta[p0 + pp] >> 16) == 0 ? Rd(0) : (Rd)src[(p0 + pp) * KS + k0 + kk];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 64 * 64; i += 256) {
@@ -350,9 +352,10 @@ inline void launch_to_position_major(hipStream_t st, long long HW, int K, int KS
 }
 
 template <class Rs, class Rd>
-inline void launch_to_atom_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst) {
+inline void launch_to_atom_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst,
+                                 const uint32_t *meta = nullptr) {
   hipLaunchKernelGGL((to_atom_major<Rs, Rd>), dim3((unsigned)((HW + 63) / 64), (unsigned)((K + 63) / 64)),
-                     dim3(256), 0, st, (int)HW, K, KS, src, dst);
+                     dim3(256), 0, st, (int)HW, K, KS, src, dst, meta);
 }
 
 template <class Rs, class Rd>
@@ -540,13 +543,16 @@ __global__ __launch_bounds__(256) void phi_kernel(Geom g, const NzEntry *__restr
 // to_position_major for the dictionary statistics: also counts the non-zeros
 // of every position into nzc and of every atom into cnt, and sets the bit of
 // every non-empty position in nzbits (all zeroed by the caller), from the
-// transposed tile.
+// transposed tile.  When one tile holds every atom (KS <= 64) the rows of
+// positions without non-zeros are not written: the statistics read z only
+// where nzc or nzbits mark a non-zero.
 template <class R>
 __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, int KS, const R *__restrict__ src,
                                                                 R *__restrict__ dst, int *__restrict__ nzc,
                                                                 unsigned int *__restrict__ cnt,
                                                                 uint32_t *__restrict__ nzbits) {
   __shared__ R tile[64][65];
+  __shared__ int pnz[64];
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int pn = (int)min(64ll, HW - p0), kn = min(64, KS - k0);
@@ -558,16 +564,13 @@ __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, i
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < pn * kn; i += 256) {
-    const int pp = i / kn, kk = i - pp * kn;
-    dst[(p0 + pp) * KS + k0 + kk] = tile[kk][pp];
-  }
   const int ka = min(kn, K - k0);  // real atoms of the tile
   if (threadIdx.x < 64) {
     const int pp = threadIdx.x;
     int c = 0;
     if (pp < pn)
       for (int kk = 0; kk < ka; ++kk) c += tile[kk][pp] != R(0);
+    pnz[pp] = c;
     if (c) atomicAdd(&nzc[p0 + pp], c);
     // the tile's 64 positions are two whole words of the bitmap (p0 is a multiple of 64)
     const unsigned long long bits = __ballot(c != 0);
@@ -581,6 +584,13 @@ __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, i
     if (kk < ka)
       for (int pp = 0; pp < pn; ++pp) c += tile[kk][pp] != R(0);
     if (c) atomicAdd(&cnt[k0 + kk], c);
+  }
+  __syncthreads();
+  const bool skip_empty = gridDim.y == 1;
+  for (int i = threadIdx.x; i < pn * kn; i += 256) {
+    const int pp = i / kn, kk = i - pp * kn;
+    if (skip_empty && pnz[pp] == 0) continue;
+    dst[(p0 + pp) * KS + k0 + kk] = tile[kk][pp];
   }
 }
 
