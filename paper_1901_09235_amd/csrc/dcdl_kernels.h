@@ -237,7 +237,9 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
 // the position's count of non-zero coordinates.  A position's 16-byte atom
 // groups are read by a segment of S lanes (S the power of two covering them,
 // at most a wave), so a wave reads contiguous memory, and the segment reduces
-// with shuffles.  z = NULL stands for z = 0 (a cold start), which is not read.
+// with shuffles; each wave takes U groups of positions per step with all
+// their loads issued first.  z = NULL stands for z = 0 (a cold start), which
+// is not read.
 template <class R>
 __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R *__restrict__ beta,
                                                   const R *__restrict__ z, const R *__restrict__ inv_n, R lambda,
@@ -245,6 +247,7 @@ __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R
                                                   uint32_t *__restrict__ meta) {
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
+  constexpr int U = 4;  // position groups per wave and step, their loads in flight together
   const int G = KS / VE;
   int S = 1;
   while (S < G && S < 64) S <<= 1;
@@ -252,39 +255,59 @@ __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R
   const long long per_wave = 64 / S;
   const long long wave = ((long long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const long long nwave = ((long long)gridDim.x * blockDim.x) >> 6;
-  for (long long p0 = wave * per_wave; p0 < HW; p0 += nwave * per_wave) {
-    const long long pos = p0 + seg;
-    R best = R(-1);
-    int bk = 0x7fffffff, nz = 0;
-    if (pos < HW)
-      for (int q = sl; q < G; q += S) {
-        const V b = *reinterpret_cast<const V *>(beta + pos * KS + q * VE);
-        const V zv = z ? *reinterpret_cast<const V *>(z + pos * KS + q * VE) : Vec<R>::zero();
+  for (long long p0 = wave * per_wave * U; p0 < HW; p0 += nwave * per_wave * U) {
+    R best[U];
+    int bk[U], nz[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      best[u] = R(-1);
+      bk[u] = 0x7fffffff;
+      nz[u] = 0;
+    }
+    for (int q = sl; q < G; q += S) {
+      V b[U], zv[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const long long pos = p0 + u * per_wave + seg;
+        b[u] = Vec<R>::zero();
+        zv[u] = Vec<R>::zero();
+        if (pos < HW) {
+          b[u] = *reinterpret_cast<const V *>(beta + pos * KS + q * VE);
+          if (z) zv[u] = *reinterpret_cast<const V *>(z + pos * KS + q * VE);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
 #pragma unroll
         for (int e = 0; e < VE; ++e) {
           const int k = q * VE + e;
           if (k >= K) break;
-          const R zk = Vec<R>::get(zv, e);
-          nz += zk != R(0);
-          const R sc = move_score(zk, st_target(Vec<R>::get(b, e), lambda, inv_n[k], positive), tol, certify);
-          if (sc > best || (sc == best && k < bk)) {
-            best = sc;
-            bk = k;
+          const R zk = Vec<R>::get(zv[u], e);
+          nz[u] += zk != R(0);
+          const R sc = move_score(zk, st_target(Vec<R>::get(b[u], e), lambda, inv_n[k], positive), tol, certify);
+          if (sc > best[u] || (sc == best[u] && k < bk[u])) {
+            best[u] = sc;
+            bk[u] = k;
           }
         }
       }
-    for (int off = S >> 1; off > 0; off >>= 1) {
-      const R ob = __shfl_xor(best, off, 64);
-      const int ok = __shfl_xor(bk, off, 64);
-      nz += __shfl_xor(nz, off, 64);
-      if (ob > best || (ob == best && ok < bk)) {
-        best = ob;
-        bk = ok;
-      }
     }
-    if (sl == 0 && pos < HW) {
-      score[pos] = best;
-      meta[pos] = (uint32_t)bk | ((uint32_t)nz << 16);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      for (int off = S >> 1; off > 0; off >>= 1) {
+        const R ob = __shfl_xor(best[u], off, 64);
+        const int ok = __shfl_xor(bk[u], off, 64);
+        nz[u] += __shfl_xor(nz[u], off, 64);
+        if (ob > best[u] || (ob == best[u] && ok < bk[u])) {
+          best[u] = ob;
+          bk[u] = ok;
+        }
+      }
+      const long long pos = p0 + u * per_wave + seg;
+      if (sl == 0 && pos < HW) {
+        score[pos] = best[u];
+        meta[pos] = (uint32_t)bk[u] | ((uint32_t)nz[u] << 16);
+      }
     }
   }
 }
@@ -294,7 +317,7 @@ inline void launch_init_moves(hipStream_t st, long long HW, int K, int KS, const
                               R lambda, R tol, int positive, int certify, R *score, uint32_t *meta) {
   int G = KS / Vec<R>::N, S = 1;
   while (S < G && S < 64) S <<= 1;
-  const long long waves = (HW + 64 / S - 1) / (64 / S);
+  const long long waves = (HW + 4 * (64 / S) - 1) / (4 * (64 / S));  // four position groups per wave
   const long long blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(init_moves<R>, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, (int)HW, K,
                      KS, beta, z, inv_n, lambda, tol, positive, certify, score, meta);
