@@ -453,11 +453,22 @@ __global__ __launch_bounds__(256) void fft_epilogue(Geom g, const double *__rest
   for (long long pos0 = blockIdx.x * 64ll; pos0 < HW; pos0 += (long long)gridDim.x * 64) {
     for (int k0 = 0; k0 < KW; k0 += 32) {
       __syncthreads();
-      for (int j = threadIdx.x; j < 32 * 64; j += 256) {
-        const int kk = j >> 6, pp = j & 63;
-        const int k = k0 + kk;
-        const long long pos = pos0 + pp;
-        t[kk][pp] = (k < g.K && pos < HW) ? G[k * HW + pos] : 0.0;
+      {
+        // the chunk's eight G reads of a thread are issued together
+        constexpr int NJ = 32 * 64 / 256;
+        double gl[NJ];
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+          const int j = threadIdx.x + 256 * jj, kk = j >> 6, pp = j & 63;
+          const int k = k0 + kk;
+          const long long pos = pos0 + pp;
+          gl[jj] = (k < g.K && pos < HW) ? G[k * HW + pos] : 0.0;
+        }
+#pragma unroll
+        for (int jj = 0; jj < NJ; ++jj) {
+          const int j = threadIdx.x + 256 * jj;
+          t[j >> 6][j & 63] = gl[jj];
+        }
       }
       __syncthreads();
       for (int j = threadIdx.x; j < 32 * 64; j += 256) {

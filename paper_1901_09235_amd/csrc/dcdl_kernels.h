@@ -334,12 +334,16 @@ __global__ __launch_bounds__(256) void to_position_major(int HW, int K, int KS, 
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int pn = (int)min(64ll, HW - p0), kn = min(64, KS - k0);
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int kk = i >> 6, pp = i & 63;
-    if (kk < kn && pp < pn) {
-      const int k = k0 + kk;
-      tile[kk][pp] = k < K ? (Rd)src[(long long)k * HW + p0 + pp] : Rd(0);
-    }
+  Rd v[16];  // a thread's 16 reads of the tile, issued together
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii, kk = i >> 6, pp = i & 63, k = k0 + kk;
+    v[ii] = kk < kn && pp < pn && k < K ? (Rd)src[(long long)k * HW + p0 + pp] : Rd(0);
+  }
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii;
+    tile[i >> 6][i & 63] = v[ii];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < pn * kn; i += 256) {
@@ -357,9 +361,17 @@ __global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, cons
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int pn = (int)min(64ll, HW - p0), kn = min(64, K - k0);
-  for (int i = threadIdx.x; i < pn * kn; i += 256) {
-    const int pp = i / kn, kk = i - pp * kn;
-    tile[kk][pp] = meta && (meta[p0 + pp] >> 16) == 0 ? Rd(0) : (Rd)src[(p0 + pp) * KS + k0 + kk];
+  Rd v[16];  // a thread's reads of the tile, issued together
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii, pp = i / kn, kk = i - pp * kn;
+    v[ii] = Rd(0);
+    if (i < pn * kn && !(meta && (meta[p0 + pp] >> 16) == 0)) v[ii] = (Rd)src[(p0 + pp) * KS + k0 + kk];
+  }
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii, pp = i / kn, kk = i - pp * kn;
+    if (i < pn * kn) tile[kk][pp] = v[ii];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < 64 * 64; i += 256) {
@@ -579,12 +591,16 @@ __global__ __launch_bounds__(256) void to_position_major_counts(int HW, int K, i
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
   const int pn = (int)min(64ll, HW - p0), kn = min(64, KS - k0);
-  for (int i = threadIdx.x; i < 64 * 64; i += 256) {
-    const int kk = i >> 6, pp = i & 63;
-    if (kk < kn && pp < pn) {
-      const int k = k0 + kk;
-      tile[kk][pp] = k < K ? src[(long long)k * HW + p0 + pp] : R(0);
-    }
+  R v[16];  // a thread's 16 reads of the tile, issued together
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii, kk = i >> 6, pp = i & 63, k = k0 + kk;
+    v[ii] = kk < kn && pp < pn && k < K ? src[(long long)k * HW + p0 + pp] : R(0);
+  }
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = threadIdx.x + 256 * ii;
+    tile[i >> 6][i & 63] = v[ii];
   }
   __syncthreads();
   const int ka = min(kn, K - k0);  // real atoms of the tile
