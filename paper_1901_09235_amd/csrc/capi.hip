@@ -1215,7 +1215,8 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
         HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
         have_ref = true;
       }
-      launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
+      launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta,
+                           meta);
       HIPCK(hipStreamSynchronize(stream));
       t_check += now_s() - tc0;
       continue;
@@ -1258,12 +1259,20 @@ int csc_impl(DeviceState *ds, hipStream_t stream, const Geom &g_user, int ndim, 
       HIPCK(hipMemcpyAsync(zref, zpm, sizeof(R) * nz, hipMemcpyDeviceToDevice, stream));
       have_ref = true;
     }
-    launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta);
+    launch_init_moves<R>(stream, HW, g.K, g.KS, beta, zpm, inv_n, lam, tol, o->positive, o->certify, score, meta,
+                         meta);
     HIPCK(hipStreamSynchronize(stream));
     t_check += now_s() - tc0;
   }
-  // the per-position non-zero counts match z unless a launch ended on a neighbour wait
-  launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out, status == DCDL_ETIMEOUT ? nullptr : meta);
+  if (status != DCDL_ETIMEOUT) {
+    // the per-position non-zero counts match z (unless a launch ended on a
+    // neighbour wait): zeros, then the positions that hold non-zeros
+    HIPCK(hipMemsetAsync(z_out, 0, sizeof(R) * (size_t)g.K * HW, stream));
+    hipLaunchKernelGGL(scatter_atom_major<R>, dim3(grid_stride_blocks(HW)), dim3(256), 0, stream, (int)HW, g.K, g.KS,
+                       (const R *)zpm, (const uint32_t *)meta, z_out);
+  } else {
+    launch_to_atom_major<R, R>(stream, HW, g.K, g.KS, zpm, z_out);
+  }
   HIPCK(hipGetLastError());
   HIPCK(hipStreamSynchronize(stream));
   if (info) {

@@ -239,12 +239,14 @@ __global__ __launch_bounds__(256) void corr_kernel(Geom g, const Rin *__restrict
 // at most a wave), so a wave reads contiguous memory, and the segment reduces
 // with shuffles; each wave takes U groups of positions per step with all
 // their loads issued first.  z = NULL stands for z = 0 (a cold start), which
-// is not read.
+// is not read.  nz_known, when given, holds counts known to match z (the
+// high 16 bits of a meta word; it may be meta itself, each word read before
+// it is rewritten): z is then read only where the count is not 0.
 template <class R>
 __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R *__restrict__ beta,
                                                   const R *__restrict__ z, const R *__restrict__ inv_n, R lambda,
                                                   R tol, int positive, int certify, R *__restrict__ score,
-                                                  uint32_t *__restrict__ meta) {
+                                                  uint32_t *meta, const uint32_t *nz_known) {
   typedef typename Vec<R>::T V;
   constexpr int VE = Vec<R>::N;
   constexpr int U = 4;  // position groups per wave and step, their loads in flight together
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R
         zv[u] = Vec<R>::zero();
         if (pos < HW) {
           b[u] = *reinterpret_cast<const V *>(beta + pos * KS + q * VE);
-          if (z) zv[u] = *reinterpret_cast<const V *>(z + pos * KS + q * VE);
+          if (z && (!nz_known || (nz_known[pos] >> 16) != 0)) zv[u] = *reinterpret_cast<const V *>(z + pos * KS + q * VE);
         }
       }
 #pragma unroll
@@ -314,13 +316,14 @@ __global__ __launch_bounds__(256) void init_moves(int HW, int K, int KS, const R
 
 template <class R>
 inline void launch_init_moves(hipStream_t st, long long HW, int K, int KS, const R *beta, const R *z, const R *inv_n,
-                              R lambda, R tol, int positive, int certify, R *score, uint32_t *meta) {
+                              R lambda, R tol, int positive, int certify, R *score, uint32_t *meta,
+                              const uint32_t *nz_known = nullptr) {
   int G = KS / Vec<R>::N, S = 1;
   while (S < G && S < 64) S <<= 1;
   const long long waves = (HW + 4 * (64 / S) - 1) / (4 * (64 / S));  // four position groups per wave
   const long long blocks = (waves + 3) / 4;
   hipLaunchKernelGGL(init_moves<R>, dim3((unsigned)(blocks < 16384 ? blocks : 16384)), dim3(256), 0, st, (int)HW, K,
-                     KS, beta, z, inv_n, lambda, tol, positive, certify, score, meta);
+                     KS, beta, z, inv_n, lambda, tol, positive, certify, score, meta, nz_known);
 }
 
 // ---------------------------------------------------------------- layouts
@@ -352,11 +355,9 @@ __global__ __launch_bounds__(256) void to_position_major(int HW, int K, int KS, 
   }
 }
 
-// With `meta` (one word per position, the high 16 bits counting its
-// non-zeros) the rows of positions without non-zeros are not read: they are 0.
 template <class Rs, class Rd>
 __global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, const Rs *__restrict__ src,
-                                                     Rd *__restrict__ dst, const uint32_t *__restrict__ meta) {
+                                                     Rd *__restrict__ dst) {
   __shared__ Rd tile[64][65];
   const long long p0 = (long long)blockIdx.x * 64;
   const int k0 = blockIdx.y * 64;
@@ -365,8 +366,7 @@ __global__ __launch_bounds__(256) void to_atom_major(int HW, int K, int KS, cons
 #pragma unroll
   for (int ii = 0; ii < 16; ++ii) {
     const int i = threadIdx.x + 256 * ii, pp = i / kn, kk = i - pp * kn;
-    v[ii] = Rd(0);
-    if (i < pn * kn && !(meta && (meta[p0 + pp] >> 16) == 0)) v[ii] = (Rd)src[(p0 + pp) * KS + k0 + kk];
+    v[ii] = i < pn * kn ? (Rd)src[(p0 + pp) * KS + k0 + kk] : Rd(0);
   }
 #pragma unroll
   for (int ii = 0; ii < 16; ++ii) {
@@ -387,10 +387,24 @@ inline void launch_to_position_major(hipStream_t st, long long HW, int K, int KS
 }
 
 template <class Rs, class Rd>
-inline void launch_to_atom_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst,
-                                 const uint32_t *meta = nullptr) {
+inline void launch_to_atom_major(hipStream_t st, long long HW, int K, int KS, const Rs *src, Rd *dst) {
   hipLaunchKernelGGL((to_atom_major<Rs, Rd>), dim3((unsigned)((HW + 63) / 64), (unsigned)((K + 63) / 64)),
-                     dim3(256), 0, st, (int)HW, K, KS, src, dst, meta);
+                     dim3(256), 0, st, (int)HW, K, KS, src, dst);
+}
+
+// The non-zeros of a position-major z written into an atom-major (K, H*W)
+// output that already holds zeros: one thread per position, and only the
+// positions whose count in `meta` (high 16 bits) is not 0 are read.
+template <class R>
+__global__ __launch_bounds__(256) void scatter_atom_major(int HW, int K, int KS, const R *__restrict__ zpm,
+                                                          const uint32_t *__restrict__ meta, R *__restrict__ dst) {
+  for (long long pos = blockIdx.x * 256ll + threadIdx.x; pos < HW; pos += (long long)gridDim.x * 256) {
+    if ((meta[pos] >> 16) == 0) continue;
+    for (int k = 0; k < K; ++k) {
+      const R v = zpm[pos * KS + k];
+      if (v != R(0)) dst[(long long)k * HW + pos] = v;
+    }
+  }
 }
 
 template <class Rs, class Rd>
