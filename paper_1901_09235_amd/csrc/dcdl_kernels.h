@@ -439,7 +439,7 @@ __global__ __launch_bounds__(256) void sum_squares(long long n, const double *__
 // has non-zeros.  Also accumulates sum |z| and the non-zero count into acc[0],
 // acc[1] (doubles).  No host round trip.
 template <class R, class Rd>
-__device__ __forceinline__ void residual_scatter(const Geom &g, long long pos, int kb, R v, const Rd *__restrict__ D,
+__device__ __forceinline__ void residual_patch(const Geom &g, long long pos, int kb, R v, const Rd *__restrict__ D,
                                                  double *__restrict__ res, double &l1, double &cnt) {
   const int lane = threadIdx.x & 63;
   unsigned long long m = __ballot(v != R(0));
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(256) void residual_dense(Geom g, const R *__restric
         for (int kb = 0; kb < g.K; kb += 64) {
           const int k = kb + lane;
           const R v = k < g.K ? z[pos * g.KS + k] : R(0);
-          residual_scatter<R, Rd>(g, pos, kb, v, D, res, l1, cnt);
+          residual_patch<R, Rd>(g, pos, kb, v, D, res, l1, cnt);
         }
       }
     }
@@ -496,7 +496,7 @@ __global__ __launch_bounds__(256) void residual_dense(Geom g, const R *__restric
 #pragma unroll
         for (int q = 0; q < RP; ++q) v[q] = (k < g.K && pos0 + q < HW) ? z[(pos0 + q) * g.KS + k] : R(0);
 #pragma unroll
-        for (int q = 0; q < RP; ++q) residual_scatter<R, Rd>(g, pos0 + q, kb, v[q], D, res, l1, cnt);
+        for (int q = 0; q < RP; ++q) residual_patch<R, Rd>(g, pos0 + q, kb, v[q], D, res, l1, cnt);
       }
     }
   }
